@@ -1,0 +1,150 @@
+"""FP64 CPU oracle of the per-pixel wRLS temporal denoiser (paper Sec. 5).
+
+TEST INFRASTRUCTURE ONLY.  This package is the reference that the GPU
+library is checked against: the C source ``wrls_oracle.c`` holds the
+arithmetic (FP64, one pixel at a time, in the order of Eq. 8, 14, 9, 11 and
+6); this module only marshals NumPy arrays into it.  Only the tests, the
+smoke check and the CPU-baseline leg of the benchmark may import it.  It
+shares no code with the GPU library.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "wrls_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+W_INVVAR = 0
+W_ONE = 1
+INTERP_BILINEAR = 0
+INTERP_NEAREST = 1
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile ``liboracle.so`` with gcc (binary64, no fast-math, no FMA
+    contraction, OpenMP over image rows)."""
+    if not force and os.path.exists(_LIB):
+        return _LIB
+    tmp = _LIB + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-std=c99", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+           "-fPIC", "-shared", "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    # A planted-mistake build of this oracle (see tests/test_oracle_mutants.py)
+    # is loaded in place of the real one when this variable names it.
+    path = os.environ.get("WRLS_ORACLE_LIB_OVERRIDE")
+    if not path:
+        path = _LIB
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+    lib = ctypes.CDLL(path)
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.oracle_create.restype = ctypes.c_void_p
+    lib.oracle_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                  ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int]
+    lib.oracle_destroy.argtypes = [ctypes.c_void_p]
+    lib.oracle_reset.argtypes = [ctypes.c_void_p]
+    lib.oracle_frames.restype = ctypes.c_long
+    lib.oracle_frames.argtypes = [ctypes.c_void_p]
+    lib.oracle_step.restype = ctypes.c_int
+    lib.oracle_step.argtypes = [ctypes.c_void_p, dp, dp, dp, dp, dp, dp,
+                                ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.oracle_get_state.argtypes = [ctypes.c_void_p, dp, dp]
+    lib.oracle_set_state.argtypes = [ctypes.c_void_p, dp, dp, ctypes.c_long]
+    _lib = lib
+    return lib
+
+
+def _f64(a, shape):
+    """Widen to a C-contiguous float64 array of the given shape (exact for
+    float16 and float32 inputs)."""
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if a.shape != tuple(shape):
+        raise ValueError("expected shape %s, got %s" % (tuple(shape), a.shape))
+    return a
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class Oracle:
+    """One denoised image sequence held in FP64.
+
+    lam: forgetting factor; delta: prior precision (P starts at I/delta,
+    beta at 0); var_floor: smallest variance turned into a weight.
+    """
+
+    def __init__(self, width, height, d, lam=0.98, delta=1.0, var_floor=1e-6,
+                 wmode=W_INVVAR, interp=INTERP_BILINEAR):
+        self._lib = _load()
+        self.W, self.H, self.d = int(width), int(height), int(d)
+        self.lam, self.delta = float(lam), float(delta)
+        h = self._lib.oracle_create(self.W, self.H, self.d, self.lam, self.delta,
+                                    float(var_floor), int(wmode), int(interp))
+        if not h:
+            raise ValueError("oracle_create rejected the parameters")
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._lib.oracle_destroy(h)
+            self._h = None
+
+    @property
+    def frames(self) -> int:
+        return int(self._lib.oracle_frames(self._h))
+
+    def reset(self):
+        self._lib.oracle_reset(self._h)
+
+    def step(self, color, feats, var, motion=None, roi=None, want_prior=False):
+        """Denoise one frame.  color (3,H,W); feats (d-1,H,W) or None when
+        d = 1; var (H,W) or None; motion (2,H,W) or None (= zero).
+        roi = (x0, y0, x1, y1) restricts the computed pixels.  Returns the
+        a-posteriori prediction (3,H,W) float64, and the a-priori one too when
+        want_prior."""
+        W, H, d = self.W, self.H, self.d
+        c = _f64(color, (3, H, W))
+        f = _f64(feats, (d - 1, H, W)) if d > 1 else None
+        v = _f64(var, (H, W)) if var is not None else None
+        m = _f64(motion, (2, H, W)) if motion is not None else None
+        out = np.zeros((3, H, W), np.float64)
+        prior = np.zeros((3, H, W), np.float64) if want_prior else None
+        x0, y0, x1, y1 = roi if roi is not None else (0, 0, W, H)
+        rc = self._lib.oracle_step(self._h, _ptr(c), _ptr(f), _ptr(v), _ptr(m), _ptr(out),
+                                   _ptr(prior), int(x0), int(y0), int(x1), int(y1))
+        if rc != 0:
+            raise ValueError("oracle_step rejected the region %r" % (roi,))
+        return (out, prior) if want_prior else out
+
+    def get_state(self):
+        """(P, beta): P (d,d,H,W) full matrices, beta (3,d,H,W)."""
+        W, H, d = self.W, self.H, self.d
+        P = np.zeros((d, d, H, W), np.float64)
+        beta = np.zeros((3, d, H, W), np.float64)
+        self._lib.oracle_get_state(self._h, _ptr(P), _ptr(beta))
+        return P, beta
+
+    def set_state(self, P, beta, frames=1):
+        W, H, d = self.W, self.H, self.d
+        P = _f64(P, (d, d, H, W))
+        beta = _f64(beta, (3, d, H, W))
+        self._lib.oracle_set_state(self._h, _ptr(P), _ptr(beta), int(frames))

@@ -1,0 +1,324 @@
+/*
+ * FP64 reference implementation of the per-pixel weighted recursive least
+ * squares (wRLS) temporal denoiser of Iglesias-Guitian, Mane and Moon,
+ * "Real-Time Denoising of Volumetric Path Tracing for Direct Volume
+ * Rendering", IEEE TVCG 2020 (arXiv 2106.08034), Sec. 5.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the oracle that the GPU library is
+ * checked against.  It is plain, slow and written to be read next to the
+ * paper: no blocking, no packing, no fusion.  It shares no code, header or
+ * constant with the GPU library; only the tests, the smoke check and the CPU
+ * baseline leg of the benchmark may load it.
+ *
+ * Arithmetic: IEEE binary64, round to nearest, built without fast-math and
+ * with -ffp-contract=off.  The one place where floating point decides an
+ * integer -- the source position j + v of the reprojection and its floor --
+ * is evaluated in binary32, the precision of the GPU kernel, so both sides
+ * pick the same taps and the same fractional weights.
+ *
+ * Per pixel j and frame t (frames counted from 0):
+ *   predictor   p = [1, f_1 .. f_{d-1}]                 (Sec. 5.1, Eq. 5)
+ *   weight      w = 1 / max(var, var_floor)  (inverse-variance mode)
+ *               w = 1                         (plain RLS, Eq. 10)
+ *               w = 0 for non-finite or negative inputs
+ *   reproject   (P, beta) <- state(t-1) at q = j + v   (Sec. 5.3, Table 2 pi)
+ *               bilinear (or nearest) on every entry; a pixel with no valid
+ *               source (t = 0, non-finite v, q outside the image) restarts at
+ *               P = I/delta, beta = 0
+ *   residual    e = y - p beta^T(t-1)                   (Eq. 8)
+ *   gain        q = P p^T / (lambda/w + p P p^T)        (Eq. 14; q = 0 at w = 0)
+ *   coeffs      beta(t) = beta(t-1) + q e               (Eq. 9)
+ *   inv. cov.   P(t) = (P - q (p P)) / lambda           (Eq. 11)
+ *   output      yhat = p beta^T(t)                      (Eq. 6, a posteriori)
+ * Colour channels share P and w and keep one beta row each (Sec. 5.1 treats
+ * channels independently with the same predictor).
+ *
+ * Parity pins: closed-form exponentially weighted least squares, the d = 1
+ * weighted mean, brute-force stacked design matrices (Eq. 7), SPD and
+ * symmetry of P, the noise-free identities, exact integer shifts and exact
+ * bilinear reprojection of bilinear state fields.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORACLE_W_INVVAR 0
+#define ORACLE_W_ONE 1
+
+#define ORACLE_INTERP_BILINEAR 0
+#define ORACLE_INTERP_NEAREST 1
+
+typedef struct oracle {
+    int W, H, d;
+    double lambda;     /* forgetting factor (Sec. 5.2) */
+    double delta;      /* prior precision: P0 = I / delta */
+    double var_floor;  /* smallest variance turned into a weight */
+    int wmode;
+    int interp;
+    long frames;       /* frames processed since creation or reset */
+    /* Per-pixel state, pixel-major: P is d*d (full, row-major), beta 3*d. */
+    double *P_cur, *beta_cur;
+    double *P_prev, *beta_prev;
+} oracle;
+
+static size_t npix(const oracle *o) { return (size_t)o->W * (size_t)o->H; }
+
+static void init_pixel(const oracle *o, double *P, double *beta)
+{
+    int d = o->d;
+    for (int i = 0; i < d; i++)
+        for (int k = 0; k < d; k++)
+            P[i * d + k] = (i == k) ? 1.0 / o->delta : 0.0;
+    for (int i = 0; i < 3 * d; i++) beta[i] = 0.0;
+}
+
+oracle *oracle_create(int W, int H, int d, double lambda, double delta,
+                      double var_floor, int wmode, int interp)
+{
+    if (W <= 0 || H <= 0 || d < 1 || d > 32) return NULL;
+    if (!(lambda > 0.0 && lambda <= 1.0) || !(delta > 0.0)) return NULL;
+    if (wmode != ORACLE_W_INVVAR && wmode != ORACLE_W_ONE) return NULL;
+    if (interp != ORACLE_INTERP_BILINEAR && interp != ORACLE_INTERP_NEAREST) return NULL;
+    oracle *o = (oracle *)calloc(1, sizeof(oracle));
+    if (!o) return NULL;
+    o->W = W; o->H = H; o->d = d;
+    o->lambda = lambda; o->delta = delta; o->var_floor = var_floor;
+    o->wmode = wmode; o->interp = interp;
+    size_t n = npix(o);
+    o->P_cur = (double *)malloc(n * d * d * sizeof(double));
+    o->P_prev = (double *)malloc(n * d * d * sizeof(double));
+    o->beta_cur = (double *)malloc(n * 3 * d * sizeof(double));
+    o->beta_prev = (double *)malloc(n * 3 * d * sizeof(double));
+    if (!o->P_cur || !o->P_prev || !o->beta_cur || !o->beta_prev) {
+        free(o->P_cur); free(o->P_prev); free(o->beta_cur); free(o->beta_prev);
+        free(o);
+        return NULL;
+    }
+    for (size_t j = 0; j < n; j++)
+        init_pixel(o, o->P_cur + j * d * d, o->beta_cur + j * 3 * d);
+    o->frames = 0;
+    return o;
+}
+
+void oracle_destroy(oracle *o)
+{
+    if (!o) return;
+    free(o->P_cur); free(o->P_prev); free(o->beta_cur); free(o->beta_prev);
+    free(o);
+}
+
+void oracle_reset(oracle *o)
+{
+    size_t n = npix(o);
+    int d = o->d;
+    for (size_t j = 0; j < n; j++)
+        init_pixel(o, o->P_cur + j * d * d, o->beta_cur + j * 3 * d);
+    o->frames = 0;
+}
+
+long oracle_frames(const oracle *o) { return o->frames; }
+
+/*
+ * Reprojection (Sec. 5.3; Table 2 defines pi(v_j) = j + v_j as the pixel
+ * position in the preceding frame).  Returns 1 and fills P, beta from the
+ * previous frame's state, or returns 0 when pixel (x, y) has no valid source.
+ * The source coordinate and its floor are taken in binary32.
+ */
+static int reproject(const oracle *o, int x, int y, double vx_in, double vy_in,
+                     double *P, double *beta)
+{
+    int d = o->d, W = o->W, H = o->H;
+    if (!isfinite(vx_in) || !isfinite(vy_in)) return 0;
+    float sx = (float)x + (float)vx_in;
+    float sy = (float)y + (float)vy_in;
+    if (!(sx >= 0.0f && sx <= (float)(W - 1) && sy >= 0.0f && sy <= (float)(H - 1)))
+        return 0;
+
+    if (o->interp == ORACLE_INTERP_NEAREST) {
+        int xn = (int)floorf(sx + 0.5f);
+        int yn = (int)floorf(sy + 0.5f);
+        if (xn > W - 1) xn = W - 1;
+        if (yn > H - 1) yn = H - 1;
+        size_t src = (size_t)yn * W + xn;
+        memcpy(P, o->P_prev + src * d * d, sizeof(double) * d * d);
+        memcpy(beta, o->beta_prev + src * 3 * d, sizeof(double) * 3 * d);
+        return 1;
+    }
+
+    /* Bilinear: the four pixels around (sx, sy), each entry of P and beta
+     * blended with the textbook weights.  At the last column/row the second
+     * tap coincides with the first (its weight is then zero anyway). */
+    float fx0 = floorf(sx), fy0 = floorf(sy);
+    int x0 = (int)fx0, y0 = (int)fy0;
+    double fx = (double)(sx - fx0), fy = (double)(sy - fy0);
+    int x1 = x0 + 1 < W ? x0 + 1 : W - 1;
+    int y1 = y0 + 1 < H ? y0 + 1 : H - 1;
+    double w00 = (1.0 - fx) * (1.0 - fy);
+    double w10 = fx * (1.0 - fy);
+    double w01 = (1.0 - fx) * fy;
+    double w11 = fx * fy;
+    size_t s00 = (size_t)y0 * W + x0, s10 = (size_t)y0 * W + x1;
+    size_t s01 = (size_t)y1 * W + x0, s11 = (size_t)y1 * W + x1;
+    for (int i = 0; i < d * d; i++)
+        P[i] = w00 * o->P_prev[s00 * d * d + i] + w10 * o->P_prev[s10 * d * d + i]
+             + w01 * o->P_prev[s01 * d * d + i] + w11 * o->P_prev[s11 * d * d + i];
+    for (int i = 0; i < 3 * d; i++)
+        beta[i] = w00 * o->beta_prev[s00 * 3 * d + i] + w10 * o->beta_prev[s10 * 3 * d + i]
+                + w01 * o->beta_prev[s01 * 3 * d + i] + w11 * o->beta_prev[s11 * 3 * d + i];
+    return 1;
+}
+
+/* Weight of the current sample: inverse variance, or 1 for plain RLS.
+ * Any non-finite input, or a negative variance, gives weight 0. */
+static double sample_weight(const oracle *o, const double *y, const double *p, double var)
+{
+    for (int c = 0; c < 3; c++)
+        if (!isfinite(y[c])) return 0.0;
+    for (int i = 0; i < o->d; i++)
+        if (!isfinite(p[i])) return 0.0;
+    if (o->wmode == ORACLE_W_ONE) return 1.0;
+    if (!isfinite(var) || var < 0.0) return 0.0;
+    double v = var > o->var_floor ? var : o->var_floor;
+    return 1.0 / v;
+}
+
+/*
+ * One wRLS update of one pixel, in place on (P, beta).  y: noisy colour,
+ * p: predictor, w: weight.  prior_out (may be NULL) receives p beta^T(t-1),
+ * out receives p beta^T(t).
+ */
+static void update_pixel(const oracle *o, double *P, double *beta, const double *p,
+                         const double *y, double w, double *prior_out, double *out)
+{
+    int d = o->d;
+    double lambda = o->lambda;
+    double Ppt[32];   /* P p^T, a column */
+    double pP[32];    /* p P, a row */
+    double q[32];
+
+    for (int i = 0; i < d; i++) {
+        double acc = 0.0;
+        for (int k = 0; k < d; k++) acc += P[i * d + k] * p[k];
+        Ppt[i] = acc;
+    }
+    for (int k = 0; k < d; k++) {
+        double acc = 0.0;
+        for (int i = 0; i < d; i++) acc += p[i] * P[i * d + k];
+        pP[k] = acc;
+    }
+    double pPpt = 0.0;
+    for (int i = 0; i < d; i++) pPpt += p[i] * Ppt[i];
+
+    /* Eq. 14.  At w = 0 the gain is its limit, zero. */
+    if (w > 0.0) {
+        double den = lambda / w + pPpt;
+        for (int i = 0; i < d; i++) q[i] = Ppt[i] / den;
+    } else {
+        for (int i = 0; i < d; i++) q[i] = 0.0;
+    }
+
+    for (int c = 0; c < 3; c++) {
+        double *b = beta + c * d;
+        double pred = 0.0;
+        for (int i = 0; i < d; i++) pred += p[i] * b[i];
+        if (prior_out) prior_out[c] = pred;
+        if (w > 0.0) {
+            double e = y[c] - pred;                       /* Eq. 8 */
+            for (int i = 0; i < d; i++) b[i] += q[i] * e;  /* Eq. 9 */
+        }
+    }
+
+    for (int i = 0; i < d; i++)                            /* Eq. 11 */
+        for (int k = 0; k < d; k++)
+            P[i * d + k] = (P[i * d + k] - q[i] * pP[k]) / lambda;
+
+    for (int c = 0; c < 3; c++) {                          /* Eq. 6 */
+        double acc = 0.0;
+        for (int i = 0; i < d; i++) acc += p[i] * beta[c * d + i];
+        out[c] = acc;
+    }
+}
+
+/*
+ * One frame.  Planar inputs, row-major planes of H*W values:
+ *   color [3][H][W], feats [d-1][H][W] (may be NULL when d = 1),
+ *   var [H][W] (ignored in unit-weight mode, may then be NULL),
+ *   motion [2][H][W] (vx then vy, pixels, backward; may be NULL = zero).
+ * out [3][H][W] receives the a-posteriori prediction, prior [3][H][W] (may be
+ * NULL) the a-priori one.  Only pixels in the half-open rectangle
+ * [x0, x1) x [y0, y1) are computed; elsewhere the state of this frame and the
+ * outputs are left unspecified.  Returns 0, or -1 on a bad rectangle.
+ */
+int oracle_step(oracle *o, const double *color, const double *feats, const double *var,
+                const double *motion, double *out, double *prior,
+                int x0, int y0, int x1, int y1)
+{
+    int W = o->W, H = o->H, d = o->d;
+    if (x0 < 0 || y0 < 0 || x1 > W || y1 > H || x0 > x1 || y0 > y1) return -1;
+    size_t n = npix(o);
+
+    /* The state of the previous frame becomes the source of this frame. */
+    double *t;
+    t = o->P_prev; o->P_prev = o->P_cur; o->P_cur = t;
+    t = o->beta_prev; o->beta_prev = o->beta_cur; o->beta_cur = t;
+    long frame = o->frames;
+
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int y = y0; y < y1; y++) {
+        for (int x = x0; x < x1; x++) {
+            size_t j = (size_t)y * W + x;
+            double *P = o->P_cur + j * d * d;
+            double *beta = o->beta_cur + j * 3 * d;
+            double p[32], yc[3], o3[3], pr3[3];
+
+            p[0] = 1.0;
+            for (int i = 1; i < d; i++) p[i] = feats[(size_t)(i - 1) * n + j];
+            for (int c = 0; c < 3; c++) yc[c] = color[(size_t)c * n + j];
+            double v = var ? var[j] : 1.0;
+            double w = sample_weight(o, yc, p, v);
+            if (w == 0.0)  /* keep non-finite predictor entries out of P */
+                for (int i = 0; i < d; i++)
+                    if (!isfinite(p[i])) p[i] = 0.0;
+
+            int have = 0;
+            if (frame > 0) {
+                double vx = motion ? motion[j] : 0.0;
+                double vy = motion ? motion[n + j] : 0.0;
+                have = reproject(o, x, y, vx, vy, P, beta);
+            }
+            if (!have) init_pixel(o, P, beta);
+
+            update_pixel(o, P, beta, p, yc, w, pr3, o3);
+            for (int c = 0; c < 3; c++) {
+                out[(size_t)c * n + j] = o3[c];
+                if (prior) prior[(size_t)c * n + j] = pr3[c];
+            }
+        }
+    }
+    o->frames = frame + 1;
+    return 0;
+}
+
+/* State export, planar: P [d][d][H][W] (full matrix), beta [3][d][H][W]. */
+void oracle_get_state(const oracle *o, double *P, double *beta)
+{
+    size_t n = npix(o);
+    int d = o->d;
+    for (size_t j = 0; j < n; j++) {
+        for (int i = 0; i < d * d; i++) P[(size_t)i * n + j] = o->P_cur[j * d * d + i];
+        for (int i = 0; i < 3 * d; i++) beta[(size_t)i * n + j] = o->beta_cur[j * 3 * d + i];
+    }
+}
+
+/* State import (same layout).  The next step reprojects from it. */
+void oracle_set_state(oracle *o, const double *P, const double *beta, long frames)
+{
+    size_t n = npix(o);
+    int d = o->d;
+    for (size_t j = 0; j < n; j++) {
+        for (int i = 0; i < d * d; i++) o->P_cur[j * d * d + i] = P[(size_t)i * n + j];
+        for (int i = 0; i < 3 * d; i++) o->beta_cur[j * 3 * d + i] = beta[(size_t)i * n + j];
+    }
+    o->frames = frames;
+}

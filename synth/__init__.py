@@ -1,0 +1,335 @@
+"""Seeded synthetic workloads for the wRLS temporal denoiser.
+
+This module only draws inputs: a procedural scene standing in for the
+paper's volume-rendered sequences (the volumes of its Table 3 and its
+1024-spp references are not available), observed through heteroscedastic
+1-spp-like noise, with the motion fields of a camera pan or a camera orbit.
+It holds none of the denoiser's arithmetic; both the GPU path and the FP64
+oracle consume exactly the arrays it returns.
+
+Scene (normalised coordinates u = x / H, v = y / H, so the image content has
+the same shape at every resolution):
+  depth D in [0.2, 1): 0.2 plus six seeded Gaussian bumps;
+  normal n = normalise(-dD/du, -dD/dv, 1);
+  albedo in [0.05, 0.95]: smooth seeded sinusoids plus three hard edges
+    (half-planes on seeded lines, each adding a seeded colour jump);
+  clean colour = albedo * (0.2 + max(0, n . l)) for a seeded light l;
+  two smooth "scattering depth" fields for the d = 10 predictor.
+Observation per frame: every feature channel gets N(0, 0.1^2) noise; the
+per-pixel variance is LogNormal(mu=-3, sigma=1) redrawn every frame; the
+noisy colour is clean + sqrt(var) * N(0, 1) per channel (one sample per
+pixel, unclamped, linear HDR).  FP16 workloads round colour and features to
+binary16 (round to nearest even); variance and motion stay FP32.
+
+Seeding: NumPy PCG64 with SeedSequence(210608034 + config index); stream s
+and frame t draw from SeedSequence(entropy, spawn_key=(s, t)).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Iterator, Optional, Tuple
+
+import numpy as np
+
+SEED_BASE = 210608034
+FEATURE_NOISE = 0.1
+VAR_MU, VAR_SIGMA = -3.0, 1.0
+
+
+@dataclasses.dataclass(frozen=True)
+class Workload:
+    """Shape and structure of one synthetic sequence."""
+    name: str
+    width: int
+    height: int
+    frames: int
+    d: int                      # predictor length, intercept included
+    in_dtype: str               # "f32" or "f16" for colour and features
+    motion: str                 # "static", "pan" or "orbit"
+    pan: Tuple[float, float] = (0.0, 0.0)   # backward motion, pixels/frame
+    disocclusion: float = 0.0   # fraction of pixels with NaN motion per frame
+    orbit_deg: float = 0.0      # camera orbit per frame (degrees)
+    lut_frame: Optional[int] = None    # transfer-function edit from this frame
+    light_frame: Optional[int] = None  # light rotation from this frame
+    config_index: int = 0       # seeds SeedSequence(SEED_BASE + config_index)
+
+    @property
+    def pixels(self) -> int:
+        return self.width * self.height
+
+    @property
+    def np_in_dtype(self):
+        return np.float16 if self.in_dtype == "f16" else np.float32
+
+
+# The five workloads: the 64x64 static correctness case, the 1080p sub-pixel
+# pan, the 4K orbit with appearance edits, the 16-stream batch and the
+# 32-session serving mix.
+def c1(**kw) -> Workload:
+    base = dict(name="c1-64x64-static-d8-f32", width=64, height=64, frames=8, d=8,
+                in_dtype="f32", motion="static", config_index=0)
+    base.update(kw)
+    return Workload(**base)
+
+
+def c2(**kw) -> Workload:
+    base = dict(name="c2-1920x1080-pan-d8-f32", width=1920, height=1080, frames=60, d=8,
+                in_dtype="f32", motion="pan", pan=(2.3, 0.0), disocclusion=0.05,
+                config_index=1)
+    base.update(kw)
+    return Workload(**base)
+
+
+def c3(**kw) -> Workload:
+    base = dict(name="c3-3840x2160-orbit-d10-f16", width=3840, height=2160, frames=30, d=10,
+                in_dtype="f16", motion="orbit", orbit_deg=0.05, lut_frame=15, light_frame=22,
+                config_index=2)
+    base.update(kw)
+    return Workload(**base)
+
+
+C4_RESOLUTIONS = ((640, 480), (1280, 720), (1920, 1080), (2560, 1440))
+C5_RESOLUTIONS = ((1280, 720), (1920, 1080), (2560, 1440), (3840, 2160))
+
+
+def c4_streams(n_streams: int = 16, frames: int = 120, scale: float = 1.0):
+    """The batched workload: n_streams pans of seeded resolution and seeded
+    direction (2.3 px/frame), FP16 inputs, d = 8.  `scale` shrinks every
+    resolution (for parity tests at small sizes)."""
+    ss = np.random.SeedSequence(SEED_BASE + 3)
+    rng = np.random.Generator(np.random.PCG64(ss))
+    out = []
+    for s in range(n_streams):
+        w, h = C4_RESOLUTIONS[int(rng.integers(len(C4_RESOLUTIONS)))]
+        ang = float(rng.uniform(0.0, 2.0 * math.pi))
+        w, h = max(8, int(round(w * scale))), max(8, int(round(h * scale)))
+        out.append(Workload(name="c4-s%02d-%dx%d" % (s, w, h), width=w, height=h,
+                            frames=frames, d=8, in_dtype="f16", motion="pan",
+                            pan=(2.3 * math.cos(ang), 2.3 * math.sin(ang)),
+                            disocclusion=0.05, config_index=3))
+    return out
+
+
+@dataclasses.dataclass
+class Frame:
+    color: np.ndarray    # (3, H, W) in_dtype
+    feats: np.ndarray    # (d-1, H, W) in_dtype
+    var: np.ndarray      # (H, W) float32
+    motion: np.ndarray   # (2, H, W) float32, NaN = disoccluded
+    clean: np.ndarray    # (3, H, W) float32, the noise-free colour
+
+
+class _Scene:
+    """Seeded procedural scene evaluated analytically at (u, v)."""
+
+    def __init__(self, rng: np.random.Generator, u_span: float):
+        lo, hi = -0.1, u_span + 0.1
+        self.bumps = [(rng.uniform(0.04, 0.13), rng.uniform(lo, hi), rng.uniform(-0.1, 1.1),
+                       rng.uniform(0.08, 0.3)) for _ in range(6)]
+        self.alb = [(rng.uniform(0.5, 3.0), rng.uniform(0, 1), rng.uniform(0.5, 3.0),
+                     rng.uniform(0, 1), rng.uniform(1.0, 4.0), rng.uniform(0, 1))
+                    for _ in range(3)]
+        self.edges = []
+        for _ in range(3):
+            th = rng.uniform(0, 2 * math.pi)
+            self.edges.append((math.cos(th), math.sin(th), rng.uniform(0.2 * u_span, 0.8 * u_span),
+                               rng.uniform(0.2, 0.8), rng.uniform(-0.3, 0.3, size=3)))
+        self.scatter = [(rng.uniform(0.5, 2.5), rng.uniform(0, 1), rng.uniform(0.5, 2.5),
+                         rng.uniform(0, 1)) for _ in range(2)]
+        l = np.array([rng.uniform(-0.5, 0.5), rng.uniform(-0.5, 0.5), 1.0])
+        self.light = l / np.linalg.norm(l)
+        knots_y = np.cumsum(rng.uniform(0.2, 1.0, size=(3, 8)), axis=1)
+        self.lut_x = np.linspace(0.0, 1.25, 8)
+        self.lut_y = 1.25 * (knots_y - knots_y[:, :1]) / (knots_y[:, -1:] - knots_y[:, :1])
+        self.lut_y = self.lut_y[:, rng.permutation(8)] * 0.5 + self.lut_y * 0.5
+
+    def depth_and_grad(self, u, v):
+        D = 0.2
+        gu = 0.0
+        gv = 0.0
+        for a, cu, cv, s in self.bumps:
+            eu = np.exp(-((u - cu) ** 2) / (2 * s * s))
+            ev = np.exp(-((v - cv) ** 2) / (2 * s * s))
+            g = a * eu * ev
+            D = D + g
+            gu = gu - g * (u - cu) / (s * s)
+            gv = gv - g * (v - cv) / (s * s)
+        return D, gu, gv
+
+    def albedo(self, u, v):
+        chans = []
+        for k1, p1, k2, p2, k3, p3 in self.alb:
+            a = 0.5 + 0.2 * np.sin(2 * math.pi * (k1 * u + p1)) * np.cos(2 * math.pi * (k2 * v + p2))
+            # sin(k3 (u + v) + p3), expanded so (1,W) x (H,1) grids stay separable
+            su, cu = np.sin(2 * math.pi * (k3 * u + p3)), np.cos(2 * math.pi * (k3 * u + p3))
+            sv, cv = np.sin(2 * math.pi * k3 * v), np.cos(2 * math.pi * k3 * v)
+            chans.append(a + 0.1 * (su * cv + cu * sv))
+        for cth, sth, pu, pv, jump in self.edges:
+            side = ((u - pu) * cth + (v - pv) * sth) > 0
+            for c in range(3):
+                chans[c] = chans[c] + jump[c] * side
+        return [np.clip(ch, 0.05, 0.95) for ch in chans]
+
+    def scatter_fields(self, u, v):
+        return [0.5 + 0.4 * np.sin(2 * math.pi * (k1 * u + p1)) * np.cos(2 * math.pi * (k2 * v + p2))
+                for k1, p1, k2, p2 in self.scatter]
+
+
+class FrameSource:
+    """Frames of one workload, generated in order (the orbit chain needs the
+    previous frame's scene coordinates)."""
+
+    def __init__(self, wl: Workload, stream: int = 0):
+        self.wl = wl
+        self.stream = stream
+        self.entropy = SEED_BASE + wl.config_index
+        rng = self._rng(0xC0FFEE)
+        W, H = wl.width, wl.height
+        pan_extent = abs(wl.pan[0]) * wl.frames + abs(wl.pan[1]) * wl.frames
+        self.scene = _Scene(rng, (W + pan_extent) / H)
+        self.t = 0
+        self._X = None  # orbit: scene pixel coordinates of every pixel
+        if wl.motion == "orbit":
+            self._orbit_flow = self._make_orbit_flow()
+
+    def _rng(self, t: int) -> np.random.Generator:
+        return np.random.Generator(np.random.PCG64(
+            np.random.SeedSequence(self.entropy, spawn_key=(self.stream, t))))
+
+    def _make_orbit_flow(self):
+        """Backward flow of a pinhole camera (60 deg horizontal FOV) orbiting
+        a pivot at depth 0.6 about the vertical axis, from the static depth
+        map of the scene at its initial position."""
+        wl = self.wl
+        W, H = wl.width, wl.height
+        x = np.arange(W, dtype=np.float64)[None, :]
+        y = np.arange(H, dtype=np.float64)[:, None]
+        D, _, _ = self.scene.depth_and_grad(x / H, y / H)
+        f = (W / 2.0) / math.tan(math.radians(30.0))
+        cx, cy = (W - 1) / 2.0, (H - 1) / 2.0
+        X = (x - cx) / f * D
+        Y = (y - cy) / f * D + 0 * x
+        Z = D + 0 * x
+        th = -math.radians(wl.orbit_deg)
+        pz = 0.6
+        Xr = math.cos(th) * X + math.sin(th) * (Z - pz)
+        Zr = -math.sin(th) * X + math.cos(th) * (Z - pz) + pz
+        xp = cx + f * Xr / Zr
+        yp = cy + f * Y / Zr
+        return np.stack([xp - x, yp - y]).astype(np.float32)
+
+    def _orbit_coords(self):
+        """Scene pixel coordinates of every pixel at the current frame:
+        X_t(x) = X_{t-1}(x + v(x)), sampled bilinearly and extended linearly
+        outside the image."""
+        wl = self.wl
+        W, H = wl.width, wl.height
+        if self._X is None:
+            xs = np.broadcast_to(np.arange(W, dtype=np.float64)[None, :], (H, W))
+            ys = np.broadcast_to(np.arange(H, dtype=np.float64)[:, None], (H, W))
+            self._X = np.stack([xs, ys]).copy()
+            return self._X
+        v = self._orbit_flow.astype(np.float64)
+        sx = np.arange(W)[None, :] + v[0]
+        sy = np.arange(H)[:, None] + v[1]
+        cxs = np.clip(sx, 0, W - 1)
+        cys = np.clip(sy, 0, H - 1)
+        x0 = np.minimum(np.floor(cxs).astype(np.int64), W - 2 if W > 1 else 0)
+        y0 = np.minimum(np.floor(cys).astype(np.int64), H - 2 if H > 1 else 0)
+        fx, fy = cxs - x0, cys - y0
+        x1, y1 = np.minimum(x0 + 1, W - 1), np.minimum(y0 + 1, H - 1)
+        new = np.empty_like(self._X)
+        for c in range(2):
+            P = self._X[c]
+            top = P[y0, x0] * (1 - fx) + P[y0, x1] * fx
+            bot = P[y1, x0] * (1 - fx) + P[y1, x1] * fx
+            new[c] = top * (1 - fy) + bot * fy
+        new[0] += sx - cxs
+        new[1] += sy - cys
+        self._X = new
+        return new
+
+    def _disocclusion_mask(self, rng, W, H):
+        frac = self.wl.disocclusion
+        mask = np.zeros((H, W), dtype=bool)
+        if frac <= 0:
+            return mask
+        r = max(2.0, 0.04 * H)
+        n = max(1, int(round(frac * W * H / (math.pi * r * r))))
+        cx = rng.uniform(0, W, size=n)
+        cy = rng.uniform(0, H, size=n)
+        for i in range(n):
+            x0, x1 = max(0, int(cx[i] - r)), min(W, int(cx[i] + r) + 1)
+            y0, y1 = max(0, int(cy[i] - r)), min(H, int(cy[i] + r) + 1)
+            if x0 >= x1 or y0 >= y1:
+                continue
+            xx = np.arange(x0, x1)[None, :]
+            yy = np.arange(y0, y1)[:, None]
+            mask[y0:y1, x0:x1] |= (xx - cx[i]) ** 2 + (yy - cy[i]) ** 2 <= r * r
+        return mask
+
+    def next(self) -> Frame:
+        wl = self.wl
+        W, H, t = wl.width, wl.height, self.t
+        rng = self._rng(t + 1)
+        sc = self.scene
+        if wl.motion == "orbit":
+            X = self._orbit_coords()
+            u, v = (X[0] / H).astype(np.float32), (X[1] / H).astype(np.float32)
+            motion = self._orbit_flow.copy()
+        else:
+            # content at frame t is the scene shifted by t * (-pan), so the
+            # previous frame holds pixel x's content at x + pan
+            u = ((np.arange(W, dtype=np.float64)[None, :] + wl.pan[0] * t) / H).astype(np.float32)
+            v = ((np.arange(H, dtype=np.float64)[:, None] + wl.pan[1] * t) / H).astype(np.float32)
+            motion = np.empty((2, H, W), np.float32)
+            motion[0] = wl.pan[0]
+            motion[1] = wl.pan[1]
+        D, gu, gv = sc.depth_and_grad(u, v)
+        D = np.broadcast_to(D, (H, W))
+        nrm = np.sqrt(gu * gu + gv * gv + 1.0)
+        n = [np.broadcast_to(-gu / nrm, (H, W)), np.broadcast_to(-gv / nrm, (H, W)),
+             np.broadcast_to(1.0 / nrm, (H, W))]
+        alb = [np.broadcast_to(a, (H, W)) for a in sc.albedo(u, v)]
+        l = sc.light
+        if wl.light_frame is not None and t >= wl.light_frame:
+            th = math.radians(60.0)
+            l = np.array([math.cos(th) * l[0] + math.sin(th) * l[2], l[1],
+                          -math.sin(th) * l[0] + math.cos(th) * l[2]])
+        l = [float(c) for c in l]
+        shade = 0.2 + np.maximum(0.0, n[0] * l[0] + n[1] * l[1] + n[2] * l[2])
+        clean = np.stack([alb[c] * shade for c in range(3)]).astype(np.float32)
+        if wl.lut_frame is not None and t >= wl.lut_frame:
+            for c in range(3):
+                clean[c] = np.interp(clean[c], sc.lut_x, sc.lut_y[c]).astype(np.float32)
+
+        feats_clean = alb + n + [D]
+        if wl.d == 10:
+            feats_clean += [np.broadcast_to(s, (H, W)) for s in sc.scatter_fields(u, v)]
+        if len(feats_clean) != wl.d - 1:
+            raise ValueError("the procedural scene provides d = 8 or d = 10 predictors")
+        feats = np.empty((wl.d - 1, H, W), np.float32)
+        for i, fc in enumerate(feats_clean):
+            feats[i] = fc + FEATURE_NOISE * rng.standard_normal((H, W), dtype=np.float32)
+        var = np.exp(VAR_MU + VAR_SIGMA * rng.standard_normal((H, W), dtype=np.float32))
+        sigma = np.sqrt(var)
+        color = clean + sigma[None] * rng.standard_normal((3, H, W), dtype=np.float32)
+        if wl.disocclusion > 0:
+            mask = self._disocclusion_mask(rng, W, H)
+            motion[:, mask] = np.nan
+        dt = wl.np_in_dtype
+        self.t += 1
+        return Frame(color=color.astype(dt), feats=feats.astype(dt), var=var.astype(np.float32),
+                     motion=motion, clean=clean)
+
+    def __iter__(self) -> Iterator[Frame]:
+        while self.t < self.wl.frames:
+            yield self.next()
+
+
+def frames(wl: Workload, stream: int = 0, count: Optional[int] = None):
+    """The first `count` (default: all) frames of a workload, as a list."""
+    src = FrameSource(wl, stream)
+    n = wl.frames if count is None else count
+    return [src.next() for _ in range(n)]

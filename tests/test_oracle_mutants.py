@@ -1,0 +1,53 @@
+"""Planted mistakes in the oracle must be caught by its pins.
+
+Each case rewrites one expression of the oracle's C source (a dropped term, a
+wrong sign, a swapped index or operand), builds that variant into a temporary
+directory, and runs the pin tests against it in a subprocess.  The pins pass
+on the real oracle (test_oracle_pins.py) and must fail on every variant.
+"""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "wrls_oracle.c")
+
+MUTANTS = {
+    "eq14_weight_inverted": ("double den = lambda / w + pPpt;", "double den = lambda * w + pPpt;"),
+    "eq14_lambda_dropped": ("double den = lambda / w + pPpt;", "double den = 1.0 / w + pPpt;"),
+    "eq8_sign": ("double e = y[c] - pred;", "double e = pred - y[c];"),
+    "eq9_sign": ("b[i] += q[i] * e;", "b[i] -= q[i] * e;"),
+    "eq11_sign": ("(P[i * d + k] - q[i] * pP[k]) / lambda", "(P[i * d + k] + q[i] * pP[k]) / lambda"),
+    "eq11_forgetting": ("(P[i * d + k] - q[i] * pP[k]) / lambda", "(P[i * d + k] - q[i] * pP[k]) * lambda"),
+    "weight_is_std": ("return 1.0 / v;", "return 1.0 / sqrt(v);"),
+    "prior_inverted": ("(i == k) ? 1.0 / o->delta : 0.0", "(i == k) ? o->delta : 0.0"),
+    "reproject_sign": ("float sx = (float)x + (float)vx_in;", "float sx = (float)x - (float)vx_in;"),
+    "bilinear_weights_swapped": ("double w10 = fx * (1.0 - fy);\n    double w01 = (1.0 - fx) * fy;",
+                                 "double w10 = (1.0 - fx) * fy;\n    double w01 = fx * (1.0 - fy);"),
+    "bilinear_tap_transposed": ("size_t s00 = (size_t)y0 * W + x0, s10 = (size_t)y0 * W + x1;",
+                                "size_t s00 = (size_t)y0 * W + x0, s10 = (size_t)y1 * W + x0;"),
+    "border_check_loose": ("sx <= (float)(W - 1)", "sx < (float)W"),
+    "nearest_truncates": ("int xn = (int)floorf(sx + 0.5f);", "int xn = (int)floorf(sx);"),
+    "output_a_priori": ("        out[c] = acc;\n", "        out[c] = prior_out ? prior_out[c] : acc;\n"),
+    "features_reversed": ("p[i] = feats[(size_t)(i - 1) * n + j];", "p[i] = feats[(size_t)(d - 1 - i) * n + j];"),
+    "outlier_not_skipped": ("    if (!isfinite(var) || var < 0.0) return 0.0;\n", ""),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_planted_mistake(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, "mutation site not found: %s" % name
+    mutant = tmp_path / "mutant.c"
+    mutant.write_text(src.replace(old, new))
+    lib = tmp_path / "libmutant.so"
+    subprocess.run(["gcc", "-std=c99", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
+                    "-w", "-o", str(lib), str(mutant), "-lm"], check=True)
+    env = dict(os.environ, WRLS_ORACLE_LIB_OVERRIDE=str(lib), OMP_NUM_THREADS="2")
+    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0, "planted mistake %r passed every pin:\n%s" % (name, r.stdout[-2000:])
