@@ -1,0 +1,181 @@
+#!/usr/bin/env python3
+"""Throughput of the wRLS temporal denoiser on one MI355X.
+
+Default workload: 1920x1080, 60 frames, 2.3 px/frame sub-pixel pan with a
+5% disocclusion mask, d = 8 predictors [1, albedo, normal, depth], FP32
+inputs and state, lambda = 0.98, heteroscedastic lognormal noise variance.
+All frames are generated (seeded, synthetic) and uploaded to HBM before the
+timed region; one step denoises one frame through the C ABI (one kernel
+launch).  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, AMD published peak
+
+
+def algorithmic_bytes_per_pixel(d: int, in_bytes: int, motion: bool = True) -> int:
+    """HBM bytes one pixel-step must move at minimum: inputs (colour 3,
+    features d-1 in the input type; variance and motion FP32), the previous
+    state read once (d(d+1)/2 + 3d floats), the new state written once, and
+    the FP32 output (3 floats)."""
+    S = d * (d + 1) // 2 + 3 * d
+    inputs = (3 + (d - 1)) * in_bytes + 4 + (8 if motion else 0)
+    return inputs + 4 * S + 4 * S + 12
+
+
+def kernel_source_hash() -> str:
+    src = os.path.join(ROOT, "paper_2106_08034_amd", "csrc", "wrls_kernels.hip")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
+
+def load_traffic(workload: str):
+    """HBM traffic per launch from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % workload)
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def make_workload(name: str):
+    import synth
+    if name == "c2":
+        return synth.c2()
+    if name == "c3":
+        return synth.c3()
+    if name == "c1":
+        return synth.c1()
+    raise SystemExit("unknown workload %r" % name)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=60)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-frames", type=int, default=0,
+                    help="frames of the oracle sample (0: all frames of the sequence)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build measures one GPU's share "
+              "(a stream or image band per GPU needs no collective); --gpus %d is not supported"
+              % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2106_08034_amd import build as hip_build
+    from paper_2106_08034_amd import wrls
+
+    if hip_build.needs_build():
+        hip_build.build()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    wl = make_workload(args.workload)
+    t0 = time.time()
+    src = synth.FrameSource(wl)
+    host_frames = []
+    dev_frames = []
+    for t in range(wl.frames):
+        f = src.next()
+        host_frames.append(f)
+        dev_frames.append(tuple(torch.from_numpy(a).to(dev) for a in (f.color, f.feats, f.var, f.motion)))
+    torch.cuda.synchronize()
+    print("generated and uploaded %d frames of %s in %.1fs" % (wl.frames, wl.name, time.time() - t0),
+          file=sys.stderr, flush=True)
+
+    stream = wrls.Stream(wl.width, wl.height, wl.d, lam=0.98, in_dtype=wl.in_dtype)
+    out = torch.empty((3, wl.height, wl.width), dtype=torch.float32, device=dev)
+    cs = torch.cuda.current_stream()
+
+    for i in range(args.warmup):
+        stream.step(*dev_frames[i % wl.frames], out=out)
+    torch.cuda.synchronize()
+
+    K = args.steps
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    ev[0].record(cs)
+    for i in range(K):
+        stream.step(*dev_frames[(args.warmup + i) % wl.frames], out=out)
+        ev[i + 1].record(cs)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    per_launch_ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(K)]
+    total_ev_ms = ev[0].elapsed_time(ev[K])
+    npix = wl.width * wl.height
+    mpix_s = K * npix / elapsed / 1e6
+    in_bytes = 2 if wl.in_dtype == "f16" else 4
+    bpp = algorithmic_bytes_per_pixel(wl.d, in_bytes, motion=wl.motion != "static")
+    avg_launch_s = float(np.mean(per_launch_ms)) / 1e3
+    achieved_gbs = bpp * npix / avg_launch_s / 1e9
+    traffic = load_traffic(args.workload)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        n_cpu = args.cpu_frames or wl.frames
+        o = oracle.Oracle(wl.width, wl.height, wl.d, lam=0.98)
+        tc = time.perf_counter()
+        for f in host_frames[:n_cpu]:
+            o.step(f.color, f.feats, f.var, f.motion)
+        cpu_s = time.perf_counter() - tc
+        cpu = {"value": round(n_cpu * npix / cpu_s / 1e6, 3), "unit": "Mpix/s",
+               "cores": oracle.threads(), "kind": "oracle",
+               "sample": "FP64 C oracle (OpenMP over rows) on the first %d frames of the same "
+                         "%s sequence, %.1f s" % (n_cpu, wl.name, cpu_s)}
+        del o
+
+    line = {
+        "metric": "denoised Mpix/s (wRLS step) + % HBM roofline",
+        "value": round(mpix_s, 2),
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed * 1e3 / K, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if wl.in_dtype == "f32" else "f32 (f16 inputs)",
+        "data": "synthetic (seeded procedural scene, lognormal per-pixel noise variance)",
+        "config": {"workload": wl.name, "width": wl.width, "height": wl.height, "d": wl.d,
+                   "frames_in_sequence": wl.frames, "lambda": 0.98,
+                   "input_dtype": wl.in_dtype, "state_dtype": "f32"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
+                     "kernel": "wrls step_kernel<%d>" % wl.d,
+                     "algorithmic_bytes_per_pixel": bpp,
+                     "avg_launch_us": round(avg_launch_s * 1e6, 2),
+                     "launch_us_min_max": [round(min(per_launch_ms) * 1e3, 2),
+                                           round(max(per_launch_ms) * 1e3, 2)],
+                     "event_total_ms": round(total_ev_ms, 3)},
+        "cpu_baseline": cpu,
+    }
+    stream.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

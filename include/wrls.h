@@ -1,0 +1,162 @@
+/*
+ * wrls.h -- C ABI of libwrls, the per-pixel weighted recursive least squares
+ * (wRLS) temporal denoiser of Iglesias-Guitian, Mane and Moon, "Real-Time
+ * Denoising of Volumetric Path Tracing for Direct Volume Rendering", IEEE
+ * TVCG 2020 (arXiv 2106.08034), built for AMD Instinct MI355X (gfx950).
+ *
+ * Problem (Sec. 5, Table 2): for every frame t, given the noisy colour
+ * I~(t), a per-pixel predictor p(t) and per-pixel velocities v, produce the
+ * denoised colour I^(t) = p(t) beta^T(t), carrying a linear model
+ * (P, beta) per pixel from frame to frame.  The model of pixel j is fetched
+ * from the previous frame at pi(v_j) = j + v_j (Sec. 5.3), then updated
+ * with RLS (Eq. 8, 9, 11) using the weighted gain of Eq. 14.
+ *
+ * Conventions shared by every call:
+ *  - Images are planar and dense, row-major: a plane holds H*W values,
+ *    x fastest; a [C][H][W] buffer holds C consecutive planes.
+ *  - The predictor is p = [1, f_1 .. f_{d-1}]: the caller supplies the d-1
+ *    feature planes, the library prepends the intercept.
+ *  - Motion is backward, in pixels: (vx, vy) at pixel (x, y) says the
+ *    content was at (x + vx, y + vy) in the previous frame.  Pixel centres
+ *    are at integer coordinates.  A non-finite component (NaN) marks a
+ *    disoccluded pixel; a source outside [0, W-1] x [0, H-1] likewise has
+ *    no history.  Such pixels, and every pixel of the first frame after
+ *    creation or reset, restart from P = I/delta, beta = 0.
+ *  - Reprojection is bilinear on every entry of P and beta (or nearest,
+ *    rounding half up).
+ *  - Weight: w = 1 / max(variance, var_floor) (inverse variance), or w = 1
+ *    (plain RLS, Eq. 10).  A non-finite colour, feature or variance, or a
+ *    negative variance, gives w = 0: the model is carried over and only
+ *    aged (P <- P / lambda, beta unchanged).
+ *  - The output is the a-posteriori prediction p(t) beta^T(t) (Eq. 6).
+ *  - Every pointer passed to a compute call is a DEVICE pointer on the
+ *    current HIP device, owned by the caller, and must stay valid until the
+ *    work enqueued on the handle's HIP stream has completed.  Calls are
+ *    stream-ordered and return without synchronising.
+ *  - Errors are reported by status code only; nothing aborts and no
+ *    exception crosses the ABI.  wrls_last_error() returns a thread-local
+ *    message for the last failing call on the calling thread.
+ *  - A handle is not re-entrant: calls on one handle must not overlap
+ *    (from several threads).  Distinct handles are independent.
+ */
+#ifndef WRLS_H
+#define WRLS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    WRLS_OK = 0,
+    WRLS_EINVAL = -1,        /* bad argument: null pointer, bad size, bad mode */
+    WRLS_ENOMEM = -2,        /* device allocation failed */
+    WRLS_EHIP = -3,          /* a HIP runtime call failed; text in wrls_last_error() */
+    WRLS_EUNSUPPORTED = -4   /* valid request this build does not implement */
+} wrls_status;
+
+typedef enum { WRLS_F32 = 0, WRLS_F16 = 1 } wrls_dtype;
+
+typedef enum {
+    WRLS_W_INVVAR = 0,  /* w = 1 / max(variance, var_floor) */
+    WRLS_W_ONE = 1      /* w = 1: plain RLS, Eq. 10 (variance may be NULL) */
+} wrls_weight_mode;
+
+typedef enum { WRLS_INTERP_BILINEAR = 0, WRLS_INTERP_NEAREST = 1 } wrls_interp;
+
+/* Largest predictor length the kernels are built for. */
+#define WRLS_MAX_D 10
+
+typedef struct {
+    int32_t width, height;  /* image size in pixels, each in [1, 16384] */
+    int32_t d;              /* predictor length incl. the intercept, 1..WRLS_MAX_D */
+    float lambda;           /* forgetting factor in (0, 1] (Sec. 5.2, Eq. 10-11) */
+    float delta;            /* prior precision > 0: P starts at I / delta */
+    float var_floor;        /* smallest variance turned into a weight, >= 0 */
+    int32_t in_dtype;       /* wrls_dtype of colour and features */
+    int32_t weight_mode;    /* wrls_weight_mode */
+    int32_t interp;         /* wrls_interp */
+    int32_t reserved[3];    /* must be zero */
+} wrls_params;
+
+typedef struct wrls_stream wrls_stream;  /* opaque, owned by the library */
+
+/* Fills *p with defaults for a width x height image and predictor length d:
+ * lambda 0.98, delta 1, var_floor 1e-6, FP32 inputs, inverse-variance
+ * weights, bilinear reprojection.  A null p is ignored. */
+void wrls_params_default(wrls_params *p, int32_t width, int32_t height, int32_t d);
+
+/* Checks a parameter block without touching the GPU: WRLS_OK or
+ * WRLS_EINVAL / WRLS_EUNSUPPORTED with a message. */
+wrls_status wrls_params_validate(const wrls_params *p);
+
+/* Floats of state per pixel: d(d+1)/2 for the packed upper triangle of P
+ * (Sec. 5.2: P is the d x d inverse covariance, symmetric) plus 3d for beta
+ * (one coefficient row per colour channel, Sec. 5.1).  0 for a bad d. */
+int32_t wrls_state_floats(int32_t d);
+
+/* Device bytes of ONE copy of the per-pixel state of a stream with these
+ * parameters (the library holds two: previous and current frame).  This is
+ * the figure a server admits streams by.  0 if the parameters are invalid. */
+size_t wrls_state_bytes(const wrls_params *p);
+
+/* Device bytes a stream allocates in total (both copies, padding). */
+size_t wrls_stream_device_bytes(const wrls_params *p);
+
+/* Creates a stream: allocates its state on the current HIP device and
+ * enqueues its initialisation on hip_stream (a hipStream_t; NULL = the
+ * default stream).  *out receives the handle.  The handle enqueues all its
+ * later work on that HIP stream. */
+wrls_status wrls_create_stream(const wrls_params *p, void *hip_stream, wrls_stream **out);
+
+/* Waits for the handle's HIP stream, frees its state and the handle.  A null
+ * handle is accepted and ignored. */
+wrls_status wrls_destroy(wrls_stream *s);
+
+/* Moves the handle's later work to another HIP stream (a hipStream_t). */
+wrls_status wrls_set_hip_stream(wrls_stream *s, void *hip_stream);
+
+/* Restarts every pixel: P = I / delta, beta = 0, frame counter 0. */
+wrls_status wrls_reset(wrls_stream *s);
+
+/* Frames processed since creation or reset (or the count passed to
+ * wrls_set_state). */
+int64_t wrls_frames(const wrls_stream *s);
+
+/* One frame (Sec. 5.2-5.3).
+ *   color    [3][H][W]    in_dtype   noisy colour I~(t), linear HDR
+ *   features [d-1][H][W]  in_dtype   predictor entries 1..d-1 (NULL iff d = 1)
+ *   variance [H][W]       float      per-pixel noise variance (NULL allowed
+ *                                    only with WRLS_W_ONE)
+ *   motion   [2][H][W]    float      vx plane then vy plane; NULL = zero
+ *   out      [3][H][W]    float      denoised colour, written
+ * Reads the state of the previous frame and writes this frame's state. */
+wrls_status wrls_step(wrls_stream *s, const void *color, const void *features,
+                      const float *variance, const float *motion, float *out);
+
+/* Copies the current state out (device pointers, stream-ordered):
+ *   P_packed [d(d+1)/2][H][W]: upper triangle of P, row-major:
+ *            (0,0), (0,1) .. (0,d-1), (1,1) .. (d-1,d-1);
+ *   beta     [3][d][H][W]: beta[c][i] multiplies predictor entry i for
+ *            colour channel c.
+ * Either pointer may be NULL to skip that part. */
+wrls_status wrls_get_state(const wrls_stream *s, float *P_packed, float *beta);
+
+/* Replaces the current state (same layout, device pointers) and sets the
+ * frame counter; with frames > 0 the next step reprojects from this state. */
+wrls_status wrls_set_state(wrls_stream *s, const float *P_packed, const float *beta,
+                           int64_t frames);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *wrls_last_error(void);
+
+/* Library version string. */
+const char *wrls_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WRLS_H */

@@ -60,6 +60,8 @@ def _load():
     lib.oracle_reset.argtypes = [ctypes.c_void_p]
     lib.oracle_frames.restype = ctypes.c_long
     lib.oracle_frames.argtypes = [ctypes.c_void_p]
+    lib.oracle_threads.restype = ctypes.c_int
+    lib.oracle_threads.argtypes = []
     lib.oracle_step.restype = ctypes.c_int
     lib.oracle_step.argtypes = [ctypes.c_void_p, dp, dp, dp, dp, dp, dp,
                                 ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
@@ -67,6 +69,11 @@ def _load():
     lib.oracle_set_state.argtypes = [ctypes.c_void_p, dp, dp, ctypes.c_long]
     _lib = lib
     return lib
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's per-row loop uses."""
+    return int(_load().oracle_threads())
 
 
 def _f64(a, shape):

@@ -39,6 +39,7 @@
  * bilinear reprojection of bilinear state fields.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -118,6 +119,9 @@ void oracle_reset(oracle *o)
 }
 
 long oracle_frames(const oracle *o) { return o->frames; }
+
+/* Threads the per-row loop of oracle_step runs on. */
+int oracle_threads(void) { return omp_get_max_threads(); }
 
 /*
  * Reprojection (Sec. 5.3; Table 2 defines pi(v_j) = j + v_j as the pixel

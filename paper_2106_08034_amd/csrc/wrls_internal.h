@@ -1,0 +1,53 @@
+// Internal declarations shared by the HIP kernels and the C ABI of libwrls.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace wrls {
+
+constexpr int kMaxD = 10;
+// Per-pixel state planes are padded to a multiple of this many floats so
+// that every plane starts on a 256-byte boundary.
+constexpr size_t kPlaneAlign = 64;
+
+__host__ __device__ constexpr int packed_floats(int d) { return d * (d + 1) / 2; }
+__host__ __device__ constexpr int state_floats(int d) { return packed_floats(d) + 3 * d; }
+
+// Position of P(i, m), i <= m, in the packed upper triangle, row-major.
+__host__ __device__ constexpr int packed_index(int d, int i, int m)
+{
+    return i * d - (i * (i - 1)) / 2 + (m - i);
+}
+
+// Everything one launch of the per-frame kernel needs for one image.
+struct FrameArgs {
+    const void *color;      // [3][H][W] float or _Float16
+    const void *feats;      // [d-1][H][W] float or _Float16
+    const float *var;       // [H][W] or null (unit weights)
+    const float *motion;    // [2][H][W] or null (zero motion)
+    float *out;             // [3][H][W]
+    const float *state_in;  // S planes of `pitch` floats (previous frame)
+    float *state_out;       // S planes of `pitch` floats (this frame)
+    int32_t W, H;
+    int64_t pitch;          // floats between state planes
+    float lambda, inv_lambda, p0, var_floor;
+    int32_t fresh;          // 1: no history (first frame)
+    int32_t unit_weight;    // 1: w = 1 (plain RLS)
+    int32_t nearest;        // 1: nearest reprojection
+    int32_t tiles_x;        // tiles per image row
+};
+
+// Launch shape of the per-frame kernel: a tile is (1 << tw_log2) pixels
+// wide and block_threads >> tw_log2 rows high; one thread per pixel.
+struct TileShape {
+    int32_t tw_log2;
+    int32_t block_threads;
+};
+
+hipError_t launch_reset(float *state, int64_t pitch, int64_t npix, int d, float p0,
+                        hipStream_t st);
+hipError_t launch_step(int d, bool f16, const FrameArgs &a, TileShape ts, hipStream_t st);
+
+}  // namespace wrls

@@ -1,0 +1,251 @@
+"""Python binding of libwrls (include/wrls.h): argument marshalling only.
+
+Every function named like the C ABI (wrls_create_stream, wrls_step, ...)
+forwards to the entry point of the same name; torch tensors supply device
+memory and torch's current HIP stream supplies the stream.  All arithmetic
+runs in the HIP kernels of libwrls.so.  There is no fallback: if the library
+is not built, or no GPU is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libwrls.so")
+
+WRLS_OK, WRLS_EINVAL, WRLS_ENOMEM, WRLS_EHIP, WRLS_EUNSUPPORTED = 0, -1, -2, -3, -4
+WRLS_F32, WRLS_F16 = 0, 1
+WRLS_W_INVVAR, WRLS_W_ONE = 0, 1
+WRLS_INTERP_BILINEAR, WRLS_INTERP_NEAREST = 0, 1
+WRLS_MAX_D = 10
+
+_STATUS_NAMES = {0: "WRLS_OK", -1: "WRLS_EINVAL", -2: "WRLS_ENOMEM", -3: "WRLS_EHIP",
+                 -4: "WRLS_EUNSUPPORTED"}
+
+
+class WrlsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (_STATUS_NAMES.get(status, str(status)), msg))
+        self.status = status
+
+
+class wrls_params(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("d", ctypes.c_int32),
+                ("lambda_", ctypes.c_float), ("delta", ctypes.c_float),
+                ("var_floor", ctypes.c_float), ("in_dtype", ctypes.c_int32),
+                ("weight_mode", ctypes.c_int32), ("interp", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
+
+
+# Every symbol include/wrls.h declares, with its ctypes signature.
+_P = ctypes.POINTER(wrls_params)
+_VP = ctypes.c_void_p
+SIGNATURES = {
+    "wrls_params_default": (None, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "wrls_params_validate": (ctypes.c_int, [_P]),
+    "wrls_state_floats": (ctypes.c_int32, [ctypes.c_int32]),
+    "wrls_state_bytes": (ctypes.c_size_t, [_P]),
+    "wrls_stream_device_bytes": (ctypes.c_size_t, [_P]),
+    "wrls_create_stream": (ctypes.c_int, [_P, _VP, ctypes.POINTER(_VP)]),
+    "wrls_destroy": (ctypes.c_int, [_VP]),
+    "wrls_set_hip_stream": (ctypes.c_int, [_VP, _VP]),
+    "wrls_reset": (ctypes.c_int, [_VP]),
+    "wrls_frames": (ctypes.c_int64, [_VP]),
+    "wrls_step": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP]),
+    "wrls_get_state": (ctypes.c_int, [_VP, _VP, _VP]),
+    "wrls_set_state": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int64]),
+    "wrls_last_error": (ctypes.c_char_p, []),
+    "wrls_version": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libwrls.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libwrls.so is not built: run __graft_entry__.build() or "
+                          "python paper_2106_08034_amd/build.py")
+    # torch loads its own HIP runtime (soname libamdhip64.so.7) under another
+    # file name; loading torch first makes libwrls bind to that same runtime
+    # instead of pulling a second copy into the process.
+    import torch  # noqa: F401
+    L = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != WRLS_OK:
+        raise WrlsError(status, lib().wrls_last_error().decode(errors="replace"))
+
+
+# ---- the C ABI, name for name -------------------------------------------
+
+def wrls_params_default(width: int, height: int, d: int) -> wrls_params:
+    p = wrls_params()
+    lib().wrls_params_default(ctypes.byref(p), width, height, d)
+    return p
+
+
+def wrls_params_validate(p: wrls_params) -> int:
+    return lib().wrls_params_validate(ctypes.byref(p))
+
+
+def wrls_state_floats(d: int) -> int:
+    return lib().wrls_state_floats(d)
+
+
+def wrls_state_bytes(p: wrls_params) -> int:
+    return lib().wrls_state_bytes(ctypes.byref(p))
+
+
+def wrls_stream_device_bytes(p: wrls_params) -> int:
+    return lib().wrls_stream_device_bytes(ctypes.byref(p))
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _current_hip_stream() -> int:
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def wrls_create_stream(p: wrls_params, hip_stream: Optional[int] = None) -> int:
+    h = ctypes.c_void_p()
+    _check(lib().wrls_create_stream(ctypes.byref(p), hip_stream, ctypes.byref(h)))
+    return h.value
+
+
+def wrls_destroy(h: int):
+    _check(lib().wrls_destroy(h))
+
+
+def wrls_set_hip_stream(h: int, hip_stream: Optional[int]):
+    _check(lib().wrls_set_hip_stream(h, hip_stream))
+
+
+def wrls_reset(h: int):
+    _check(lib().wrls_reset(h))
+
+
+def wrls_frames(h: int) -> int:
+    return lib().wrls_frames(h)
+
+
+def wrls_step(h: int, color, features, variance, motion, out):
+    _check(lib().wrls_step(h, _ptr(color), _ptr(features), _ptr(variance), _ptr(motion),
+                           _ptr(out)))
+
+
+def wrls_get_state(h: int, P_packed, beta):
+    _check(lib().wrls_get_state(h, _ptr(P_packed), _ptr(beta)))
+
+
+def wrls_set_state(h: int, P_packed, beta, frames: int):
+    _check(lib().wrls_set_state(h, _ptr(P_packed), _ptr(beta), frames))
+
+
+def wrls_last_error() -> str:
+    return lib().wrls_last_error().decode(errors="replace")
+
+
+def wrls_version() -> str:
+    return lib().wrls_version().decode()
+
+
+# ---- convenience wrapper over torch tensors -------------------------------
+
+_DTYPES = {"f32": WRLS_F32, "f16": WRLS_F16}
+_WMODES = {"invvar": WRLS_W_INVVAR, "one": WRLS_W_ONE}
+_INTERPS = {"bilinear": WRLS_INTERP_BILINEAR, "nearest": WRLS_INTERP_NEAREST}
+
+
+class Stream:
+    """One image sequence whose per-pixel models live on the GPU.
+
+    All work is enqueued on the torch stream current at creation (or the
+    one passed); tensors must be contiguous, on the current device, with the
+    shapes documented in include/wrls.h.
+    """
+
+    def __init__(self, width: int, height: int, d: int, lam: float = 0.98, delta: float = 1.0,
+                 var_floor: float = 1e-6, in_dtype: str = "f32", weight_mode: str = "invvar",
+                 interp: str = "bilinear", hip_stream: Optional[int] = None):
+        import torch
+        self._torch = torch
+        p = wrls_params_default(width, height, d)
+        p.lambda_, p.delta, p.var_floor = lam, delta, var_floor
+        p.in_dtype, p.weight_mode, p.interp = _DTYPES[in_dtype], _WMODES[weight_mode], _INTERPS[interp]
+        self.params = p
+        self.W, self.H, self.d = width, height, d
+        self.in_dtype = torch.float16 if in_dtype == "f16" else torch.float32
+        self.hip_stream = _current_hip_stream() if hip_stream is None else hip_stream
+        self.handle = wrls_create_stream(p, self.hip_stream)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # interpreter shutdown: the runtime may be gone
+            pass
+
+    def close(self):
+        h = getattr(self, "handle", None)
+        if h:
+            self.handle = None
+            wrls_destroy(h)
+
+    @property
+    def frames(self) -> int:
+        return wrls_frames(self.handle)
+
+    def _chk(self, t, shape, dtype, name):
+        if t is None:
+            return None
+        if not t.is_cuda or t.dtype != dtype or tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+            raise ValueError("%s: expected contiguous %s %s on the GPU, got %s %s %s"
+                             % (name, dtype, tuple(shape), t.dtype, tuple(t.shape), t.device))
+        return t
+
+    def step(self, color, features, variance, motion=None, out=None):
+        torch = self._torch
+        W, H, d = self.W, self.H, self.d
+        self._chk(color, (3, H, W), self.in_dtype, "color")
+        if d > 1:
+            self._chk(features, (d - 1, H, W), self.in_dtype, "features")
+        self._chk(variance, (H, W), torch.float32, "variance")
+        self._chk(motion, (2, H, W), torch.float32, "motion")
+        if out is None:
+            out = torch.empty((3, H, W), dtype=torch.float32, device=color.device)
+        self._chk(out, (3, H, W), torch.float32, "out")
+        wrls_step(self.handle, color, features if d > 1 else None, variance, motion, out)
+        return out
+
+    def reset(self):
+        wrls_reset(self.handle)
+
+    def get_state(self) -> Tuple["object", "object"]:
+        torch = self._torch
+        W, H, d = self.W, self.H, self.d
+        P = torch.empty((d * (d + 1) // 2, H, W), dtype=torch.float32, device="cuda")
+        B = torch.empty((3, d, H, W), dtype=torch.float32, device="cuda")
+        wrls_get_state(self.handle, P, B)
+        return P, B
+
+    def set_state(self, P_packed, beta, frames: int = 1):
+        torch = self._torch
+        W, H, d = self.W, self.H, self.d
+        self._chk(P_packed, (d * (d + 1) // 2, H, W), torch.float32, "P_packed")
+        self._chk(beta, (3, d, H, W), torch.float32, "beta")
+        wrls_set_state(self.handle, P_packed, beta, frames)

@@ -21,8 +21,10 @@ noisy colour is clean + sqrt(var) * N(0, 1) per channel (one sample per
 pixel, unclamped, linear HDR).  FP16 workloads round colour and features to
 binary16 (round to nearest even); variance and motion stay FP32.
 
-Seeding: NumPy PCG64 with SeedSequence(210608034 + config index); stream s
-and frame t draw from SeedSequence(entropy, spawn_key=(s, t)).
+Seeding: NumPy PCG64 with SeedSequence(210608034 + config index); the scene
+of stream s comes from spawn_key (s, 0xC0FFEE), the noise of frame t in the
+band of rows starting at r0 from spawn_key (s, t + 1, r0), and the
+disocclusion discs of frame t from spawn_key (s, t + 1).
 """
 from __future__ import annotations
 
@@ -118,6 +120,24 @@ class Frame:
     var: np.ndarray      # (H, W) float32
     motion: np.ndarray   # (2, H, W) float32, NaN = disoccluded
     clean: np.ndarray    # (3, H, W) float32, the noise-free colour
+    color_f32: Optional[np.ndarray] = None  # colour before FP16 rounding (on request)
+    feats_f32: Optional[np.ndarray] = None  # features before FP16 rounding (on request)
+
+
+# Frames are generated in bands of rows, each with its own seeded noise, in a
+# thread pool (NumPy releases the GIL inside its array kernels).
+BAND_ROWS = 32
+_POOL = None
+
+
+def _pool():
+    global _POOL
+    if _POOL is None:
+        import concurrent.futures
+        import os
+        n = min(16, os.cpu_count() or 1)
+        _POOL = concurrent.futures.ThreadPoolExecutor(max_workers=n) if n > 1 else False
+    return _POOL or None
 
 
 class _Scene:
@@ -230,23 +250,35 @@ class FrameSource:
             ys = np.broadcast_to(np.arange(H, dtype=np.float64)[:, None], (H, W))
             self._X = np.stack([xs, ys]).copy()
             return self._X
-        v = self._orbit_flow.astype(np.float64)
-        sx = np.arange(W)[None, :] + v[0]
-        sy = np.arange(H)[:, None] + v[1]
-        cxs = np.clip(sx, 0, W - 1)
-        cys = np.clip(sy, 0, H - 1)
-        x0 = np.minimum(np.floor(cxs).astype(np.int64), W - 2 if W > 1 else 0)
-        y0 = np.minimum(np.floor(cys).astype(np.int64), H - 2 if H > 1 else 0)
-        fx, fy = cxs - x0, cys - y0
-        x1, y1 = np.minimum(x0 + 1, W - 1), np.minimum(y0 + 1, H - 1)
-        new = np.empty_like(self._X)
-        for c in range(2):
-            P = self._X[c]
-            top = P[y0, x0] * (1 - fx) + P[y0, x1] * fx
-            bot = P[y1, x0] * (1 - fx) + P[y1, x1] * fx
-            new[c] = top * (1 - fy) + bot * fy
-        new[0] += sx - cxs
-        new[1] += sy - cys
+        prev = self._X
+        new = np.empty_like(prev)
+
+        def band(b):
+            r0, r1 = b
+            v = self._orbit_flow[:, r0:r1].astype(np.float64)
+            sx = np.arange(W)[None, :] + v[0]
+            sy = np.arange(r0, r1)[:, None] + v[1]
+            cxs = np.clip(sx, 0, W - 1)
+            cys = np.clip(sy, 0, H - 1)
+            x0 = np.minimum(np.floor(cxs).astype(np.int64), W - 2 if W > 1 else 0)
+            y0 = np.minimum(np.floor(cys).astype(np.int64), H - 2 if H > 1 else 0)
+            fx, fy = cxs - x0, cys - y0
+            x1, y1 = np.minimum(x0 + 1, W - 1), np.minimum(y0 + 1, H - 1)
+            for c in range(2):
+                P = prev[c]
+                top = P[y0, x0] * (1 - fx) + P[y0, x1] * fx
+                bot = P[y1, x0] * (1 - fx) + P[y1, x1] * fx
+                new[c, r0:r1] = top * (1 - fy) + bot * fy
+            new[0, r0:r1] += sx - cxs
+            new[1, r0:r1] += sy - cys
+
+        bands = [(r0, min(H, r0 + BAND_ROWS)) for r0 in range(0, H, BAND_ROWS)]
+        pool = _pool()
+        if pool is None:
+            for b in bands:
+                band(b)
+        else:
+            list(pool.map(band, bands))
         self._X = new
         return new
 
@@ -269,59 +301,93 @@ class FrameSource:
             mask[y0:y1, x0:x1] |= (xx - cx[i]) ** 2 + (yy - cy[i]) ** 2 <= r * r
         return mask
 
-    def next(self) -> Frame:
+    def _band(self, t, r0, r1, u, v, l, out):
+        """Scene and noise of rows [r0, r1): fills the frame arrays in `out`.
+        Each band draws its noise from its own seeded generator, so the
+        result does not depend on how bands are scheduled."""
+        wl = self.wl
+        W = wl.width
+        h = r1 - r0
+        sc = self.scene
+        rng = np.random.Generator(np.random.PCG64(
+            np.random.SeedSequence(self.entropy, spawn_key=(self.stream, t + 1, r0))))
+        D, gu, gv = sc.depth_and_grad(u, v)
+        D = np.broadcast_to(D, (h, W))
+        nrm = np.sqrt(gu * gu + gv * gv + 1.0)
+        n = [np.broadcast_to(-gu / nrm, (h, W)), np.broadcast_to(-gv / nrm, (h, W)),
+             np.broadcast_to(1.0 / nrm, (h, W))]
+        alb = [np.broadcast_to(a, (h, W)) for a in sc.albedo(u, v)]
+        shade = 0.2 + np.maximum(0.0, n[0] * l[0] + n[1] * l[1] + n[2] * l[2])
+        clean = out["clean"][:, r0:r1]
+        for c in range(3):
+            clean[c] = alb[c] * shade
+            if wl.lut_frame is not None and t >= wl.lut_frame:
+                clean[c] = np.interp(clean[c], sc.lut_x, sc.lut_y[c])
+        feats_clean = alb + n + [D]
+        if wl.d == 10:
+            feats_clean += [np.broadcast_to(s_, (h, W)) for s_ in sc.scatter_fields(u, v)]
+        feats = out["feats32"][:, r0:r1]
+        for i, fc in enumerate(feats_clean):
+            feats[i] = fc + FEATURE_NOISE * rng.standard_normal((h, W), dtype=np.float32)
+        var = np.exp(VAR_MU + VAR_SIGMA * rng.standard_normal((h, W), dtype=np.float32))
+        out["var"][r0:r1] = var
+        out["color32"][:, r0:r1] = clean + np.sqrt(var)[None] * rng.standard_normal((3, h, W), dtype=np.float32)
+
+    def next(self, keep_unrounded: bool = False) -> Frame:
         wl = self.wl
         W, H, t = wl.width, wl.height, self.t
-        rng = self._rng(t + 1)
-        sc = self.scene
+        if wl.d not in (8, 10):
+            raise ValueError("the procedural scene provides d = 8 or d = 10 predictors")
         if wl.motion == "orbit":
             X = self._orbit_coords()
-            u, v = (X[0] / H).astype(np.float32), (X[1] / H).astype(np.float32)
+            U, V = (X[0] / H).astype(np.float32), (X[1] / H).astype(np.float32)
             motion = self._orbit_flow.copy()
         else:
             # content at frame t is the scene shifted by t * (-pan), so the
             # previous frame holds pixel x's content at x + pan
-            u = ((np.arange(W, dtype=np.float64)[None, :] + wl.pan[0] * t) / H).astype(np.float32)
-            v = ((np.arange(H, dtype=np.float64)[:, None] + wl.pan[1] * t) / H).astype(np.float32)
+            U = ((np.arange(W, dtype=np.float64)[None, :] + wl.pan[0] * t) / H).astype(np.float32)
+            V = ((np.arange(H, dtype=np.float64)[:, None] + wl.pan[1] * t) / H).astype(np.float32)
             motion = np.empty((2, H, W), np.float32)
             motion[0] = wl.pan[0]
             motion[1] = wl.pan[1]
-        D, gu, gv = sc.depth_and_grad(u, v)
-        D = np.broadcast_to(D, (H, W))
-        nrm = np.sqrt(gu * gu + gv * gv + 1.0)
-        n = [np.broadcast_to(-gu / nrm, (H, W)), np.broadcast_to(-gv / nrm, (H, W)),
-             np.broadcast_to(1.0 / nrm, (H, W))]
-        alb = [np.broadcast_to(a, (H, W)) for a in sc.albedo(u, v)]
-        l = sc.light
+        l = self.scene.light
         if wl.light_frame is not None and t >= wl.light_frame:
             th = math.radians(60.0)
             l = np.array([math.cos(th) * l[0] + math.sin(th) * l[2], l[1],
                           -math.sin(th) * l[0] + math.cos(th) * l[2]])
         l = [float(c) for c in l]
-        shade = 0.2 + np.maximum(0.0, n[0] * l[0] + n[1] * l[1] + n[2] * l[2])
-        clean = np.stack([alb[c] * shade for c in range(3)]).astype(np.float32)
-        if wl.lut_frame is not None and t >= wl.lut_frame:
-            for c in range(3):
-                clean[c] = np.interp(clean[c], sc.lut_x, sc.lut_y[c]).astype(np.float32)
+        out = {"clean": np.empty((3, H, W), np.float32),
+               "feats32": np.empty((wl.d - 1, H, W), np.float32),
+               "var": np.empty((H, W), np.float32),
+               "color32": np.empty((3, H, W), np.float32)}
+        bands = [(r0, min(H, r0 + BAND_ROWS)) for r0 in range(0, H, BAND_ROWS)]
 
-        feats_clean = alb + n + [D]
-        if wl.d == 10:
-            feats_clean += [np.broadcast_to(s, (H, W)) for s in sc.scatter_fields(u, v)]
-        if len(feats_clean) != wl.d - 1:
-            raise ValueError("the procedural scene provides d = 8 or d = 10 predictors")
-        feats = np.empty((wl.d - 1, H, W), np.float32)
-        for i, fc in enumerate(feats_clean):
-            feats[i] = fc + FEATURE_NOISE * rng.standard_normal((H, W), dtype=np.float32)
-        var = np.exp(VAR_MU + VAR_SIGMA * rng.standard_normal((H, W), dtype=np.float32))
-        sigma = np.sqrt(var)
-        color = clean + sigma[None] * rng.standard_normal((3, H, W), dtype=np.float32)
+        def work(b):
+            r0, r1 = b
+            if U.shape[0] == 1:
+                u = U
+            else:
+                u = U[r0:r1]
+            v = V[r0:r1]
+            self._band(t, r0, r1, u, v, l, out)
+
+        pool = _pool()
+        if pool is None or len(bands) == 1:
+            for b in bands:
+                work(b)
+        else:
+            list(pool.map(work, bands))
         if wl.disocclusion > 0:
+            rng = self._rng(t + 1)
             mask = self._disocclusion_mask(rng, W, H)
             motion[:, mask] = np.nan
         dt = wl.np_in_dtype
         self.t += 1
-        return Frame(color=color.astype(dt), feats=feats.astype(dt), var=var.astype(np.float32),
-                     motion=motion, clean=clean)
+        fr = Frame(color=out["color32"].astype(dt), feats=out["feats32"].astype(dt), var=out["var"],
+                   motion=motion, clean=out["clean"])
+        if keep_unrounded:
+            fr.color_f32, fr.feats_f32 = out["color32"], out["feats32"]
+        return fr
 
     def __iter__(self) -> Iterator[Frame]:
         while self.t < self.wl.frames:

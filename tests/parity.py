@@ -1,0 +1,98 @@
+"""Helpers for the GPU-vs-oracle parity tests: error measures and a runner
+that feeds the same seeded frames to the HIP path and to the FP64 oracle.
+
+Tolerance (FP32 state against the FP64 oracle, inputs identical):
+  G1 output:  max |y_gpu - y_ref| / max(|y_ref|, tau) <= 1e-4, with
+              tau = 1e-3 * RMS(y_ref of that frame);
+  G2 P:       per pixel ||P_gpu - P_ref||_F / ||P_ref||_F <= 1e-4;
+  G3 beta:    in prediction space, |p . (beta_gpu - beta_ref)_c| /
+              max(|p . beta_ref_c|, tau) <= 1e-4.
+"""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+
+G1_TOL = 1e-4
+G2_TOL = 1e-4
+G3_TOL = 1e-4
+
+
+def log(msg: str):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def g1(gpu: np.ndarray, ref: np.ndarray) -> float:
+    tau = 1e-3 * float(np.sqrt(np.mean(ref.astype(np.float64) ** 2)))
+    den = np.maximum(np.abs(ref), max(tau, 1e-30))
+    return float(np.max(np.abs(gpu.astype(np.float64) - ref) / den)) if ref.size else 0.0
+
+
+def unpack_P(P_packed: np.ndarray, d: int) -> np.ndarray:
+    """(d(d+1)/2, H, W) upper triangle, row-major -> (d, d, H, W) symmetric."""
+    H, W = P_packed.shape[1:]
+    P = np.zeros((d, d, H, W), np.float64)
+    k = 0
+    for i in range(d):
+        for m in range(i, d):
+            P[i, m] = P_packed[k]
+            P[m, i] = P_packed[k]
+            k += 1
+    return P
+
+
+def g2(P_gpu_packed: np.ndarray, P_ref: np.ndarray) -> float:
+    d = P_ref.shape[0]
+    Pg = unpack_P(P_gpu_packed, d)
+    num = np.sqrt(np.sum((Pg - P_ref) ** 2, axis=(0, 1)))
+    den = np.sqrt(np.sum(P_ref ** 2, axis=(0, 1)))
+    return float(np.max(num / den))
+
+
+def g3(beta_gpu: np.ndarray, beta_ref: np.ndarray, p: np.ndarray) -> float:
+    """p: (d, H, W) predictor of the last frame (intercept included)."""
+    yg = np.einsum("cdhw,dhw->chw", beta_gpu.astype(np.float64), p)
+    yr = np.einsum("cdhw,dhw->chw", beta_ref, p)
+    return g1(yg, yr)
+
+
+def predictor(feats: np.ndarray) -> np.ndarray:
+    H, W = feats.shape[1:]
+    return np.concatenate([np.ones((1, H, W)), feats.astype(np.float64)])
+
+
+def to_dev(a: np.ndarray):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+class Pair:
+    """A GPU stream and an oracle fed identical frames."""
+
+    def __init__(self, W, H, d, lam=0.98, delta=1.0, var_floor=1e-6, in_dtype="f32",
+                 weight_mode="invvar", interp="bilinear"):
+        import oracle
+        from paper_2106_08034_amd import wrls
+        self.gpu = wrls.Stream(W, H, d, lam=lam, delta=delta, var_floor=var_floor,
+                               in_dtype=in_dtype, weight_mode=weight_mode, interp=interp)
+        self.ref = oracle.Oracle(W, H, d, lam=lam, delta=delta, var_floor=var_floor,
+                                 wmode={"invvar": oracle.W_INVVAR, "one": oracle.W_ONE}[weight_mode],
+                                 interp={"bilinear": oracle.INTERP_BILINEAR,
+                                         "nearest": oracle.INTERP_NEAREST}[interp])
+        self.d = d
+
+    def step(self, color, feats, var, motion):
+        out = self.gpu.step(to_dev(color), to_dev(feats) if self.d > 1 else None,
+                            None if var is None else to_dev(var),
+                            None if motion is None else to_dev(motion))
+        ref = self.ref.step(color, feats if self.d > 1 else None, var, motion)
+        return out.cpu().numpy(), ref
+
+    def state_errors(self, last_feats):
+        Pg, Bg = self.gpu.get_state()
+        Pr, Br = self.ref.get_state()
+        Pg, Bg = Pg.cpu().numpy(), Bg.cpu().numpy()
+        p = predictor(last_feats) if self.d > 1 else np.ones((1,) + Pr.shape[2:])
+        return g2(Pg, Pr), g3(Bg, Br, p)

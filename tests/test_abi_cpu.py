@@ -1,0 +1,107 @@
+"""The C ABI without a GPU: the library loads, exports every symbol the
+header declares, and rejects bad arguments with status codes before any HIP
+call is made."""
+import ctypes
+import os
+import re
+import threading
+
+import pytest
+
+from paper_2106_08034_amd import wrls
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "wrls.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return set(re.findall(r"^[A-Za-z_][\w\s\*]*?\b(wrls_\w+)\s*\(", src, flags=re.M))
+
+
+def test_header_symbols_exported_and_bound():
+    names = _declared()
+    assert {"wrls_create_stream", "wrls_step", "wrls_destroy"} <= names
+    L = wrls.lib()
+    for n in sorted(names):
+        assert hasattr(L, n), "libwrls.so does not export %s" % n
+        assert n in wrls.SIGNATURES, "the binding does not declare %s" % n
+        assert callable(getattr(wrls, n)), "the binding has no function %s" % n
+    assert set(wrls.SIGNATURES) == names
+
+
+def test_state_sizes():
+    for d in range(1, 11):
+        assert wrls.wrls_state_floats(d) == d * (d + 1) // 2 + 3 * d
+    assert wrls.wrls_state_floats(0) == 0
+    assert wrls.wrls_state_floats(11) == 0
+    p = wrls.wrls_params_default(1920, 1080, 8)
+    assert wrls.wrls_state_bytes(p) == 240 * 1920 * 1080
+    assert wrls.wrls_stream_device_bytes(p) >= 2 * 240 * 1920 * 1080
+    p = wrls.wrls_params_default(3840, 2160, 10)
+    assert wrls.wrls_state_bytes(p) == 340 * 3840 * 2160
+
+
+def test_defaults():
+    p = wrls.wrls_params_default(64, 48, 8)
+    assert (p.width, p.height, p.d) == (64, 48, 8)
+    assert abs(p.lambda_ - 0.98) < 1e-7 and p.delta == 1.0 and abs(p.var_floor - 1e-6) < 1e-12
+    assert p.in_dtype == wrls.WRLS_F32 and p.weight_mode == wrls.WRLS_W_INVVAR
+    assert p.interp == wrls.WRLS_INTERP_BILINEAR
+    assert wrls.wrls_params_validate(p) == wrls.WRLS_OK
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("width", 0, wrls.WRLS_EINVAL), ("height", 16385, wrls.WRLS_EINVAL),
+    ("width", -3, wrls.WRLS_EINVAL), ("d", 0, wrls.WRLS_EUNSUPPORTED),
+    ("d", 11, wrls.WRLS_EUNSUPPORTED), ("lambda_", 0.0, wrls.WRLS_EINVAL),
+    ("lambda_", 1.5, wrls.WRLS_EINVAL), ("lambda_", float("nan"), wrls.WRLS_EINVAL),
+    ("delta", 0.0, wrls.WRLS_EINVAL), ("delta", float("inf"), wrls.WRLS_EINVAL),
+    ("var_floor", -1.0, wrls.WRLS_EINVAL), ("in_dtype", 7, wrls.WRLS_EINVAL),
+    ("weight_mode", 5, wrls.WRLS_EINVAL), ("interp", 2, wrls.WRLS_EINVAL),
+])
+def test_bad_params_rejected_without_gpu(field, value, status):
+    p = wrls.wrls_params_default(64, 48, 8)
+    setattr(p, field, value)
+    assert wrls.wrls_params_validate(p) == status
+    assert wrls.wrls_last_error()
+    assert wrls.wrls_state_bytes(p) == 0
+    h = ctypes.c_void_p(123)
+    rc = wrls.lib().wrls_create_stream(ctypes.byref(p), None, ctypes.byref(h))
+    assert rc == status and h.value is None
+
+
+def test_reserved_must_be_zero():
+    p = wrls.wrls_params_default(8, 8, 8)
+    p.reserved[1] = 1
+    assert wrls.wrls_params_validate(p) == wrls.WRLS_EINVAL
+
+
+def test_null_arguments():
+    L = wrls.lib()
+    assert L.wrls_params_validate(None) == wrls.WRLS_EINVAL
+    p = wrls.wrls_params_default(8, 8, 8)
+    assert L.wrls_create_stream(ctypes.byref(p), None, None) == wrls.WRLS_EINVAL
+    assert L.wrls_destroy(None) == wrls.WRLS_OK
+    assert L.wrls_reset(None) == wrls.WRLS_EINVAL
+    assert L.wrls_frames(None) == -1
+    assert L.wrls_step(None, None, None, None, None, None) == wrls.WRLS_EINVAL
+    assert L.wrls_get_state(None, None, None) == wrls.WRLS_EINVAL
+    assert L.wrls_set_state(None, None, None, 0) == wrls.WRLS_EINVAL
+    assert L.wrls_set_hip_stream(None, None) == wrls.WRLS_EINVAL
+    L.wrls_params_default(None, 1, 1, 1)  # ignored, must not crash
+    with pytest.raises(wrls.WrlsError):
+        wrls.wrls_reset(None)
+
+
+def test_last_error_is_thread_local():
+    p = wrls.wrls_params_default(8, 8, 8)
+    p.d = 99
+    wrls.wrls_params_validate(p)
+    mine = wrls.wrls_last_error()
+    seen = []
+    t = threading.Thread(target=lambda: seen.append(wrls.wrls_last_error()))
+    t.start()
+    t.join()
+    assert "d = 99" in mine and seen == [""]
