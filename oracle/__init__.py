@@ -66,6 +66,7 @@ def _load():
     lib.oracle_step.argtypes = [ctypes.c_void_p, dp, dp, dp, dp, dp, dp,
                                 ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.oracle_get_state.argtypes = [ctypes.c_void_p, dp, dp]
+    lib.oracle_get_beta.argtypes = [ctypes.c_void_p, dp]
     lib.oracle_set_state.argtypes = [ctypes.c_void_p, dp, dp, ctypes.c_long]
     _lib = lib
     return lib
@@ -149,6 +150,12 @@ class Oracle:
         beta = np.zeros((3, d, H, W), np.float64)
         self._lib.oracle_get_state(self._h, _ptr(P), _ptr(beta))
         return P, beta
+
+    def get_beta(self):
+        """beta (3,d,H,W) alone."""
+        beta = np.zeros((3, self.d, self.H, self.W), np.float64)
+        self._lib.oracle_get_beta(self._h, _ptr(beta))
+        return beta
 
     def set_state(self, P, beta, frames=1):
         W, H, d = self.W, self.H, self.d

@@ -315,6 +315,15 @@ void oracle_get_state(const oracle *o, double *P, double *beta)
     }
 }
 
+/* beta alone, planar [3][d][H][W]. */
+void oracle_get_beta(const oracle *o, double *beta)
+{
+    size_t n = npix(o);
+    int d = o->d;
+    for (size_t j = 0; j < n; j++)
+        for (int i = 0; i < 3 * d; i++) beta[(size_t)i * n + j] = o->beta_cur[j * 3 * d + i];
+}
+
 /* State import (same layout).  The next step reprojects from it. */
 void oracle_set_state(oracle *o, const double *P, const double *beta, long frames)
 {

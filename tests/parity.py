@@ -2,11 +2,18 @@
 that feeds the same seeded frames to the HIP path and to the FP64 oracle.
 
 Tolerance (FP32 state against the FP64 oracle, inputs identical):
-  G1 output:  max |y_gpu - y_ref| / max(|y_ref|, tau) <= 1e-4, with
-              tau = 1e-3 * RMS(y_ref of that frame);
+  G1 output:  max over pixels, channels and frames of
+                  |y_gpu - y_ref| / max(s, tau) <= 1e-4,
+              where s = sum_i |p_i beta_ref,c,i| is the magnitude of the terms
+              the prediction y = p beta_c^T sums (s >= |y_ref|, and s = |y_ref|
+              when no term cancels), and tau = 1e-3 * RMS(y_ref of that frame)
+              guards exact zeros.  The FP32 rounding error of the prediction
+              is proportional to s, not to |y|: where the terms cancel to
+              nearly zero, a bound relative to |y| alone would ask for more
+              than FP32 resolution of the terms.
   G2 P:       per pixel ||P_gpu - P_ref||_F / ||P_ref||_F <= 1e-4;
-  G3 beta:    in prediction space, |p . (beta_gpu - beta_ref)_c| /
-              max(|p . beta_ref_c|, tau) <= 1e-4.
+  G3 beta:    in prediction space with the last frame's predictor,
+              |p . (beta_gpu - beta_ref)_c| / max(s, tau) <= 1e-4.
 """
 from __future__ import annotations
 
@@ -24,10 +31,21 @@ def log(msg: str):
     sys.stdout.flush()
 
 
-def g1(gpu: np.ndarray, ref: np.ndarray) -> float:
+def term_scale(beta_ref: np.ndarray, p: np.ndarray) -> np.ndarray:
+    """sum_i |p_i beta_c,i| per channel and pixel: beta_ref (3,d,H,W), p (d,H,W)."""
+    return np.einsum("dhw,cdhw->chw", np.abs(p), np.abs(beta_ref))
+
+
+def g1(gpu: np.ndarray, ref: np.ndarray, scale=None) -> float:
+    """Max relative error of gpu against ref; the denominator is the term
+    scale when given (see the module docstring), else |ref|, floored at
+    1e-3 * RMS(ref)."""
+    if not ref.size:
+        return 0.0
     tau = 1e-3 * float(np.sqrt(np.mean(ref.astype(np.float64) ** 2)))
-    den = np.maximum(np.abs(ref), max(tau, 1e-30))
-    return float(np.max(np.abs(gpu.astype(np.float64) - ref) / den)) if ref.size else 0.0
+    den = np.abs(ref) if scale is None else np.maximum(np.abs(ref), scale)
+    den = np.maximum(den, max(tau, 1e-30))
+    return float(np.max(np.abs(gpu.astype(np.float64) - ref) / den))
 
 
 def unpack_P(P_packed: np.ndarray, d: int) -> np.ndarray:
@@ -55,7 +73,15 @@ def g3(beta_gpu: np.ndarray, beta_ref: np.ndarray, p: np.ndarray) -> float:
     """p: (d, H, W) predictor of the last frame (intercept included)."""
     yg = np.einsum("cdhw,dhw->chw", beta_gpu.astype(np.float64), p)
     yr = np.einsum("cdhw,dhw->chw", beta_ref, p)
-    return g1(yg, yr)
+    return g1(yg, yr, term_scale(beta_ref, p))
+
+
+def beta_normwise(beta_gpu: np.ndarray, beta_ref: np.ndarray) -> float:
+    """Reported, not gated: per pixel and channel ||dbeta|| / ||beta_ref||
+    (limited by the conditioning of P, not by the kernel)."""
+    num = np.sqrt(np.sum((beta_gpu.astype(np.float64) - beta_ref) ** 2, axis=1))
+    den = np.sqrt(np.sum(beta_ref ** 2, axis=1))
+    return float(np.max(num / np.maximum(den, 1e-30)))
 
 
 def predictor(feats: np.ndarray) -> np.ndarray:
@@ -84,15 +110,23 @@ class Pair:
         self.d = d
 
     def step(self, color, feats, var, motion):
+        """One frame on both sides: (gpu output, oracle output, G1 error)."""
         out = self.gpu.step(to_dev(color), to_dev(feats) if self.d > 1 else None,
                             None if var is None else to_dev(var),
                             None if motion is None else to_dev(motion))
         ref = self.ref.step(color, feats if self.d > 1 else None, var, motion)
-        return out.cpu().numpy(), ref
+        p = predictor(feats) if self.d > 1 else np.ones((1,) + ref.shape[1:])
+        # non-finite predictor entries enter the model as 0 (weight-0 frames)
+        p = np.where(np.isfinite(p), p, 0.0)
+        scale = term_scale(self.ref.get_beta(), p)
+        out = out.cpu().numpy()
+        return out, ref, g1(out, ref, scale)
 
     def state_errors(self, last_feats):
+        """(G2, G3, normwise beta error) of the current state."""
         Pg, Bg = self.gpu.get_state()
         Pr, Br = self.ref.get_state()
         Pg, Bg = Pg.cpu().numpy(), Bg.cpu().numpy()
         p = predictor(last_feats) if self.d > 1 else np.ones((1,) + Pr.shape[2:])
-        return g2(Pg, Pr), g3(Bg, Br, p)
+        p = np.where(np.isfinite(p), p, 0.0)
+        return g2(Pg, Pr), g3(Bg, Br, p), beta_normwise(Bg, Br)

@@ -4,13 +4,11 @@ Bar: G1/G2/G3 <= 1e-4 (see tests/parity.py) for floating point; bitwise
 equality where the method is exact (reset == fresh stream, state
 export/import, zero-weight ageing of a constant state).
 """
-import math
-
 import numpy as np
 import pytest
 
 import synth
-from parity import G1_TOL, G2_TOL, G3_TOL, Pair, g1, log, to_dev
+from parity import G1_TOL, G2_TOL, G3_TOL, Pair, g1, log, predictor, term_scale, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -33,16 +31,16 @@ def _run(wl, frames=None, check_state=True, **kw):
     for t in range(n):
         f = src.next()
         log("case %s frame %d/%d" % (wl.name, t + 1, n))
-        out, ref = pair.step(f.color, f.feats, f.var, f.motion)
-        e = g1(out, ref)
+        out, ref, e = pair.step(f.color, f.feats, f.var, f.motion)
         worst = max(worst, e)
         assert e <= G1_TOL, "frame %d: G1 %.3g" % (t, e)
-    e2 = e3 = None
+    e2 = e3 = eb = None
     if check_state:
-        e2, e3 = pair.state_errors(f.feats)
+        e2, e3, eb = pair.state_errors(f.feats)
         assert e2 <= G2_TOL, "G2 %.3g" % e2
         assert e3 <= G3_TOL, "G3 %.3g" % e3
-    log("case %s: worst G1 %.3g, G2 %s, G3 %s" % (wl.name, worst, e2, e3))
+    log("case %s: worst G1 %.3g, G2 %s, G3 %s, beta normwise (reported) %s"
+        % (wl.name, worst, e2, e3, eb))
     return worst
 
 
@@ -62,8 +60,9 @@ def test_c3_orbit_fp16_d10_with_edits_small():
 
 def test_c3_fp16_error_against_unrounded_inputs_reported():
     """FP16 inputs: the error of the GPU run against an oracle fed the
-    unrounded FP32 inputs is reported (it measures input rounding, not the
-    kernel) and stays far below the noise level."""
+    unrounded FP32 inputs is reported.  It measures the binary16 rounding of
+    colour and features (relative 2^-11 per value), not the kernel, and stays
+    within a small multiple of that rounding on the term scale."""
     import oracle
     from paper_2106_08034_amd import wrls
     wl = synth.c3(width=96, height=64, frames=12)
@@ -75,9 +74,10 @@ def test_c3_fp16_error_against_unrounded_inputs_reported():
         f = src.next(keep_unrounded=True)
         out = g.step(to_dev(f.color), to_dev(f.feats), to_dev(f.var), to_dev(f.motion)).cpu().numpy()
         ref = o32.step(f.color_f32, f.feats_f32, f.var, f.motion)
-        worst = max(worst, g1(out, ref))
-    log("FP16 inputs vs unrounded-FP32 oracle: max rel error %.3g" % worst)
-    assert worst < 5e-2
+        scale = term_scale(o32.get_beta(), predictor(f.feats_f32))
+        worst = max(worst, g1(out, ref, scale))
+    log("FP16 inputs vs unrounded-FP32 oracle: max rel error (term scale) %.3g" % worst)
+    assert worst < 50 * 2.0 ** -11
 
 
 @pytest.mark.parametrize("d", list(range(1, 11)))
@@ -94,9 +94,9 @@ def test_modes_and_every_d(d, interp, weight_mode):
         var = np.exp(-3 + rng.standard_normal((H, W))).astype(np.float32)
         motion = rng.uniform(-1.6, 1.6, size=(2, H, W)).astype(np.float32)
         motion[:, rng.random((H, W)) < 0.05] = np.nan
-        out, ref = pair.step(color, feats, var if weight_mode == "invvar" else None, motion)
-        assert g1(out, ref) <= G1_TOL
-    e2, e3 = pair.state_errors(feats)
+        out, ref, e = pair.step(color, feats, var if weight_mode == "invvar" else None, motion)
+        assert e <= G1_TOL, e
+    e2, e3, _ = pair.state_errors(feats)
     assert e2 <= G2_TOL and e3 <= G3_TOL
 
 
@@ -124,10 +124,10 @@ def test_edge_cases_nonfinite_inputs_and_borders():
         motion[:, 3, 3] = (0.0, -np.inf)
         motion[:, 4, 4] = (-4.5, 0.0)               # left of the image
         motion[:, 5, 5] = (0.0, np.nan)
-        out, ref = pair.step(color, feats, var, motion)
+        out, ref, e = pair.step(color, feats, var, motion)
         assert np.all(np.isfinite(out))
-        assert g1(out, ref) <= G1_TOL
-    e2, e3 = pair.state_errors(feats)
+        assert e <= G1_TOL, e
+    e2, e3, _ = pair.state_errors(feats)
     assert e2 <= G2_TOL and e3 <= G3_TOL
 
 
@@ -142,8 +142,8 @@ def test_degenerate_and_maximum_shapes(W, H):
         color = rng.uniform(0, 1.5, size=(3, H, W)).astype(np.float32)
         var = np.exp(-3 + rng.standard_normal((H, W))).astype(np.float32)
         motion = rng.uniform(-1.2, 1.2, size=(2, H, W)).astype(np.float32)
-        out, ref = pair.step(color, feats, var, motion)
-        assert g1(out, ref) <= G1_TOL
+        out, ref, e = pair.step(color, feats, var, motion)
+        assert e <= G1_TOL, e
 
 
 def test_reset_equals_fresh_and_state_roundtrip_bitwise():
