@@ -89,7 +89,10 @@ typedef struct wrls_stream wrls_stream;  /* opaque, owned by the library */
 void wrls_params_default(wrls_params *p, int32_t width, int32_t height, int32_t d);
 
 /* Checks a parameter block without touching the GPU: WRLS_OK or
- * WRLS_EINVAL / WRLS_EUNSUPPORTED with a message. */
+ * WRLS_EINVAL / WRLS_EUNSUPPORTED with a message.  Besides the ranges noted
+ * in wrls_params, one copy of a stream's state (wrls_state_floats(d) floats
+ * per pixel, planes padded to 64 floats) must stay below 4 GiB: e.g. up to
+ * about 17.9 Mpixel at d = 8 and 12.6 Mpixel at d = 10 (3840x2160 is 8.3). */
 wrls_status wrls_params_validate(const wrls_params *p);
 
 /* Floats of state per pixel: d(d+1)/2 for the packed upper triangle of P
@@ -117,6 +120,16 @@ wrls_status wrls_destroy(wrls_stream *s);
 
 /* Moves the handle's later work to another HIP stream (a hipStream_t). */
 wrls_status wrls_set_hip_stream(wrls_stream *s, void *hip_stream);
+
+/* Launch shape of the per-frame kernel (the autotuner's knob): one thread
+ * per pixel, workgroups of block_threads in {64, 128, 256} threads covering a
+ * tile (1 << tile_w_log2) pixels wide and block_threads >> tile_w_log2 rows
+ * high; tile_w_log2 in [0, log2(block_threads)].  Results do not depend on
+ * the shape (each pixel's arithmetic is the same).  Default: 128 x 2. */
+wrls_status wrls_set_tile(wrls_stream *s, int32_t tile_w_log2, int32_t block_threads);
+
+/* Reads back the launch shape. */
+wrls_status wrls_get_tile(const wrls_stream *s, int32_t *tile_w_log2, int32_t *block_threads);
 
 /* Restarts every pixel: P = I / delta, beta = 0, frame counter 0. */
 wrls_status wrls_reset(wrls_stream *s);

@@ -47,7 +47,7 @@ int64_t plane_pitch(const wrls_params *p)
     return (n + a - 1) / a * a;
 }
 
-wrls::TileShape default_tile() { return wrls::TileShape{6, 256}; }
+wrls::TileShape default_tile() { return wrls::TileShape{7, 256}; }
 
 }  // namespace
 
@@ -89,6 +89,14 @@ wrls_status wrls_params_validate(const wrls_params *p)
         return fail(WRLS_EINVAL, "interp = %d unknown", p->interp);
     for (int i = 0; i < 3; i++)
         if (p->reserved[i] != 0) return fail(WRLS_EINVAL, "reserved fields must be zero");
+    // The kernels address every array with 32-bit byte offsets; the state
+    // copy is the largest array of a stream.
+    const uint64_t copy = (uint64_t)wrls::state_floats(p->d) * sizeof(float) *
+                          (uint64_t)plane_pitch(p);
+    if (copy > 0xFFFFFFFFull)
+        return fail(WRLS_EUNSUPPORTED,
+                    "%dx%d at d = %d needs %llu bytes per state copy; the limit is 4 GiB - 1",
+                    p->width, p->height, p->d, (unsigned long long)copy);
     return WRLS_OK;
 }
 
@@ -160,6 +168,25 @@ wrls_status wrls_set_hip_stream(wrls_stream *s, void *hip_stream)
 {
     if (!s) return fail(WRLS_EINVAL, "stream handle is NULL");
     s->st = static_cast<hipStream_t>(hip_stream);
+    return WRLS_OK;
+}
+
+wrls_status wrls_set_tile(wrls_stream *s, int32_t tile_w_log2, int32_t block_threads)
+{
+    if (!s) return fail(WRLS_EINVAL, "stream handle is NULL");
+    if (block_threads != 64 && block_threads != 128 && block_threads != 256)
+        return fail(WRLS_EINVAL, "block_threads = %d not in {64, 128, 256}", block_threads);
+    if (tile_w_log2 < 0 || (1 << tile_w_log2) > block_threads)
+        return fail(WRLS_EINVAL, "tile width 2^%d exceeds %d threads", tile_w_log2, block_threads);
+    s->tile = wrls::TileShape{tile_w_log2, block_threads};
+    return WRLS_OK;
+}
+
+wrls_status wrls_get_tile(const wrls_stream *s, int32_t *tile_w_log2, int32_t *block_threads)
+{
+    if (!s || !tile_w_log2 || !block_threads) return fail(WRLS_EINVAL, "NULL argument");
+    *tile_w_log2 = s->tile.tw_log2;
+    *block_threads = s->tile.block_threads;
     return WRLS_OK;
 }
 

@@ -22,6 +22,13 @@ namespace wrls {
 namespace {
 
 constexpr int kNumXcd = 8;
+// Cache policy of the streaming stores (state, output): non-temporal, so the
+// written lines do not displace the gathered previous-frame state in L2.
+constexpr int kStorePolicy = 2;
+// Planes whose bilinear taps are loaded together (see update_pixel).  Without
+// the grouping (and the scheduling barrier that keeps it) the compiler
+// serialises the d = 10 gather to a few loads in flight per wave.
+constexpr int kGatherGroup = 4;
 
 // Workgroups are dispatched to the XCDs round-robin (block b runs on XCD
 // b % 8).  Map block b to a tile index so that each XCD processes one
@@ -36,8 +43,40 @@ __device__ __forceinline__ int xcd_tile(int b, int nblocks)
     return start + idx;
 }
 
-__device__ __forceinline__ float load_in(const float *p, size_t i) { return p[i]; }
-__device__ __forceinline__ float load_in(const _Float16 *p, size_t i) { return (float)p[i]; }
+// Every access goes through a raw buffer descriptor of one whole array
+// (built once, in scalar registers) with the plane offset as the scalar
+// offset and a 32-bit per-lane byte offset.  The address needs no per-lane
+// 64-bit math, and an access past the array reads 0 / is dropped instead of
+// faulting.  The host guarantees every array is below 4 GiB.
+using Rsrc = __amdgpu_buffer_rsrc_t;
+constexpr int kRawBufferWord3 = 0x00020000;  // gfx9-family raw buffer, 32-bit data
+
+__device__ __forceinline__ Rsrc array_rsrc(const void *base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes,
+                                             kRawBufferWord3);
+}
+__device__ __forceinline__ float bload(Rsrc r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(float,
+                              __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ void bstore(Rsrc r, uint32_t voff, uint32_t soff, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff,
+                                          (int)soff, kStorePolicy);
+}
+// Element j of plane `plane` of an input array of planes of n values.
+__device__ __forceinline__ float load_in(Rsrc r, const float *, uint32_t n, int plane, uint32_t j)
+{
+    return bload(r, j * 4u, (uint32_t)plane * n * 4u);
+}
+__device__ __forceinline__ float load_in(Rsrc r, const _Float16 *, uint32_t n, int plane, uint32_t j)
+{
+    const uint16_t h = __builtin_amdgcn_raw_buffer_load_b16(r, (int)(j * 2u),
+                                                           (int)((uint32_t)plane * n * 2u), 0);
+    return (float)__builtin_bit_cast(_Float16, h);
+}
 
 __device__ __forceinline__ bool finite(float v) { return __builtin_isfinite(v); }
 
@@ -47,19 +86,21 @@ __device__ __forceinline__ void update_pixel(const FrameArgs &a, int x, int y)
 {
     constexpr int NP = packed_floats(D);
     constexpr int NB = 3 * D;
-    const size_t n = (size_t)a.W * (size_t)a.H;
-    const size_t j = (size_t)y * a.W + x;
-    const InT *color = static_cast<const InT *>(a.color);
-    const InT *feats = static_cast<const InT *>(a.feats);
+    const uint32_t n = (uint32_t)a.W * (uint32_t)a.H;
+    const uint32_t j = (uint32_t)y * (uint32_t)a.W + (uint32_t)x;
+    const InT *tag = nullptr;  // selects the input type's loader
+    const uint32_t in_bytes = n * (uint32_t)sizeof(InT);
+    const Rsrc r_color = array_rsrc(a.color, 3u * in_bytes);
+    const Rsrc r_feats = array_rsrc(a.feats, (uint32_t)(D - 1) * in_bytes);
 
     // Inputs: predictor p = [1, features], noisy colour, variance.
     float p[D];
     p[0] = 1.0f;
 #pragma unroll
-    for (int i = 1; i < D; i++) p[i] = load_in(feats, (size_t)(i - 1) * n + j);
+    for (int i = 1; i < D; i++) p[i] = load_in(r_feats, tag, n, i - 1, j);
     float yc[3];
 #pragma unroll
-    for (int c = 0; c < 3; c++) yc[c] = load_in(color, (size_t)c * n + j);
+    for (int c = 0; c < 3; c++) yc[c] = load_in(r_color, tag, n, c, j);
 
     // Weight: inverse variance (or 1); 0 for any non-finite input.
     bool ok = finite(yc[0]) && finite(yc[1]) && finite(yc[2]);
@@ -69,7 +110,7 @@ __device__ __forceinline__ void update_pixel(const FrameArgs &a, int x, int y)
     if (a.unit_weight) {
         w = ok ? 1.0f : 0.0f;
     } else {
-        const float v = a.var[j];
+        const float v = bload(array_rsrc(a.var, n * 4u), j * 4u, 0u);
         ok = ok && finite(v) && v >= 0.0f;
         w = ok ? 1.0f / fmaxf(v, a.var_floor) : 0.0f;
     }
@@ -84,40 +125,63 @@ __device__ __forceinline__ void update_pixel(const FrameArgs &a, int x, int y)
     if (!a.fresh) {
         float vx = 0.0f, vy = 0.0f;
         if (a.motion) {
-            vx = a.motion[j];
-            vy = a.motion[n + j];
+            const Rsrc r_mot = array_rsrc(a.motion, 2u * n * 4u);
+            vx = bload(r_mot, j * 4u, 0u);
+            vy = bload(r_mot, j * 4u, n * 4u);
         }
         const float sx = (float)x + vx;
         const float sy = (float)y + vy;
         // NaN fails every comparison and +-inf lands outside: both restart.
         have = sx >= 0.0f && sx <= (float)(a.W - 1) && sy >= 0.0f && sy <= (float)(a.H - 1);
         if (have) {
-            const float *src = a.state_in;
-            const size_t pitch = (size_t)a.pitch;
+            const uint32_t pbytes = (uint32_t)a.pitch * 4u;
+            const Rsrc src = array_rsrc(a.state_in, (uint32_t)(NP + NB) * pbytes);
             if (a.nearest) {
                 const int xn = min((int)floorf(sx + 0.5f), a.W - 1);
                 const int yn = min((int)floorf(sy + 0.5f), a.H - 1);
-                const size_t s0 = (size_t)yn * a.W + xn;
+                const uint32_t o = ((uint32_t)yn * (uint32_t)a.W + (uint32_t)xn) * 4u;
 #pragma unroll
-                for (int k = 0; k < NP; k++) P[k] = src[(size_t)k * pitch + s0];
+                for (int k = 0; k < NP; k++) P[k] = bload(src, o, (uint32_t)k * pbytes);
 #pragma unroll
-                for (int k = 0; k < NB; k++) B[k] = src[(size_t)(NP + k) * pitch + s0];
+                for (int k = 0; k < NB; k++) B[k] = bload(src, o, (uint32_t)(NP + k) * pbytes);
             } else {
                 const float fx0 = floorf(sx), fy0 = floorf(sy);
                 const float fx = sx - fx0, fy = sy - fy0;
                 const int x0 = (int)fx0, y0 = (int)fy0;
                 const int x1 = min(x0 + 1, a.W - 1), y1 = min(y0 + 1, a.H - 1);
-                const size_t s00 = (size_t)y0 * a.W + x0, s10 = (size_t)y0 * a.W + x1;
-                const size_t s01 = (size_t)y1 * a.W + x0, s11 = (size_t)y1 * a.W + x1;
-                // Bilinear in nested-lerp form: exact for a constant field.
+                const uint32_t W = (uint32_t)a.W;
+                const uint32_t o00 = ((uint32_t)y0 * W + (uint32_t)x0) * 4u;
+                const uint32_t o10 = ((uint32_t)y0 * W + (uint32_t)x1) * 4u;
+                const uint32_t o01 = ((uint32_t)y1 * W + (uint32_t)x0) * 4u;
+                const uint32_t o11 = ((uint32_t)y1 * W + (uint32_t)x1) * 4u;
+                // Bilinear in nested-lerp form (exact for a constant field).
+                // Planes go in groups of kGatherGroup: the group's 4 * kGatherGroup
+                // loads are issued back to back, so many are in flight per wave,
+                // before any of them is consumed.
 #pragma unroll
-                for (int k = 0; k < NP + NB; k++) {
-                    const float *pl = src + (size_t)k * pitch;
-                    const float v00 = pl[s00], v10 = pl[s10], v01 = pl[s01], v11 = pl[s11];
-                    const float top = fmaf(fx, v10 - v00, v00);
-                    const float bot = fmaf(fx, v11 - v01, v01);
-                    const float v = fmaf(fy, bot - top, top);
-                    if (k < NP) P[k] = v; else B[k - NP] = v;
+                for (int k0 = 0; k0 < NP + NB; k0 += kGatherGroup) {
+                    float t00[kGatherGroup], t10[kGatherGroup], t01[kGatherGroup], t11[kGatherGroup];
+#pragma unroll
+                    for (int g = 0; g < kGatherGroup; g++) {
+                        if (k0 + g < NP + NB) {
+                            const uint32_t so = (uint32_t)(k0 + g) * pbytes;
+                            t00[g] = bload(src, o00, so);
+                            t10[g] = bload(src, o10, so);
+                            t01[g] = bload(src, o01, so);
+                            t11[g] = bload(src, o11, so);
+                        }
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int g = 0; g < kGatherGroup; g++) {
+                        const int k = k0 + g;
+                        if (k < NP + NB) {
+                            const float top = fmaf(fx, t10[g] - t00[g], t00[g]);
+                            const float bot = fmaf(fx, t11[g] - t01[g], t01[g]);
+                            const float v = fmaf(fy, bot - top, top);
+                            if (k < NP) P[k] = v; else B[k - NP] = v;
+                        }
+                    }
                 }
             }
         }
@@ -177,14 +241,16 @@ __device__ __forceinline__ void update_pixel(const FrameArgs &a, int x, int y)
         }
     }
 
-    float *dst = a.state_out;
-    const size_t pitch = (size_t)a.pitch;
+    const uint32_t pbytes = (uint32_t)a.pitch * 4u;
+    const Rsrc dst = array_rsrc(a.state_out, (uint32_t)(NP + NB) * pbytes);
+    const Rsrc r_out = array_rsrc(a.out, 3u * n * 4u);
+    const uint32_t oj = j * 4u;
 #pragma unroll
-    for (int k = 0; k < NP; k++) dst[(size_t)k * pitch + j] = P[k];
+    for (int k = 0; k < NP; k++) bstore(dst, oj, (uint32_t)k * pbytes, P[k]);
 #pragma unroll
-    for (int k = 0; k < NB; k++) dst[(size_t)(NP + k) * pitch + j] = B[k];
+    for (int k = 0; k < NB; k++) bstore(dst, oj, (uint32_t)(NP + k) * pbytes, B[k]);
 #pragma unroll
-    for (int c = 0; c < 3; c++) a.out[(size_t)c * n + j] = out[c];
+    for (int c = 0; c < 3; c++) bstore(r_out, oj, (uint32_t)c * n * 4u, out[c]);
 }
 
 template <int D, typename InT>

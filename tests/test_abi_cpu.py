@@ -72,6 +72,21 @@ def test_bad_params_rejected_without_gpu(field, value, status):
     assert rc == status and h.value is None
 
 
+def test_state_copy_limit_4gib():
+    p = wrls.wrls_params_default(16384, 16384, 10)
+    assert wrls.wrls_params_validate(p) == wrls.WRLS_EUNSUPPORTED
+    assert "4 GiB" in wrls.wrls_last_error()
+    p = wrls.wrls_params_default(3840, 2160, 10)
+    assert wrls.wrls_params_validate(p) == wrls.WRLS_OK
+    # the largest square image at d = 10 whose state copy fits
+    S = wrls.wrls_state_floats(10)
+    side = int(((2 ** 32 - 1) // (4 * S)) ** 0.5) // 8 * 8
+    while (side * side + 63) // 64 * 64 * 4 * S > 2 ** 32 - 1:
+        side -= 8
+    assert wrls.wrls_params_validate(wrls.wrls_params_default(side, side, 10)) == wrls.WRLS_OK
+    assert wrls.wrls_params_validate(wrls.wrls_params_default(side + 64, side + 64, 10)) == wrls.WRLS_EUNSUPPORTED
+
+
 def test_reserved_must_be_zero():
     p = wrls.wrls_params_default(8, 8, 8)
     p.reserved[1] = 1
@@ -90,6 +105,8 @@ def test_null_arguments():
     assert L.wrls_get_state(None, None, None) == wrls.WRLS_EINVAL
     assert L.wrls_set_state(None, None, None, 0) == wrls.WRLS_EINVAL
     assert L.wrls_set_hip_stream(None, None) == wrls.WRLS_EINVAL
+    assert L.wrls_set_tile(None, 6, 256) == wrls.WRLS_EINVAL
+    assert L.wrls_get_tile(None, None, None) == wrls.WRLS_EINVAL
     L.wrls_params_default(None, 1, 1, 1)  # ignored, must not crash
     with pytest.raises(wrls.WrlsError):
         wrls.wrls_reset(None)

@@ -204,3 +204,46 @@ def test_c2_full_size_1080p_all_60_frames():
 
 def test_c3_full_size_4k_first_frames():
     _run(synth.c3(frames=5))
+
+
+def _max_square_side(d):
+    from paper_2106_08034_amd import wrls
+    side = 16384
+    while wrls.wrls_params_validate(wrls.wrls_params_default(side, side, d)) != 0:
+        side -= 16
+    return side
+
+
+def test_maximum_size_d10_sampled_windows():
+    """The largest square image a d = 10 stream accepts (state copy just
+    below 4 GiB), FP16 inputs, a sub-pixel pan.  A pixel's model depends only
+    on the pixels its motion chain visits, so crops whose chains stay inside
+    them are run through small oracles and compared pixel by pixel."""
+    import oracle
+    import torch
+    from paper_2106_08034_amd import wrls
+    side = _max_square_side(10)
+    T, d, vx = 3, 10, 2.3
+    wl = synth.c3(width=side, height=side, frames=T, motion="pan", pan=(vx, 0.0), lut_frame=None,
+                  light_frame=None)
+    log("case max size %dx%d d=10 (%.1f Mpixel)" % (side, side, side * side / 1e6))
+    g = wrls.Stream(side, side, d, in_dtype="f16")
+    src = synth.FrameSource(wl)
+    wins = [(0, 0), (side - 48, side - 6), (side // 2 + 5, side // 3), (side - 8 - int(vx * T) - 3, 7)]
+    w, h = 40, 6
+    crops = [(x0, y0, min(side, x0 + w + int(vx * T) + 3), y0 + h) for (x0, y0) in wins]
+    oracles = [oracle.Oracle(c[2] - c[0], c[3] - c[1], d) for c in crops]
+    for t in range(T):
+        f = src.next()
+        out = g.step(to_dev(f.color), to_dev(f.feats), to_dev(f.var), to_dev(f.motion))
+        torch.cuda.synchronize()
+        for (x0, y0, x1, y1), o in zip(crops, oracles):
+            ref = o.step(f.color[:, y0:y1, x0:x1], f.feats[:, y0:y1, x0:x1], f.var[y0:y1, x0:x1],
+                         f.motion[:, y0:y1, x0:x1])
+            scale = term_scale(o.get_beta(), predictor(f.feats[:, y0:y1, x0:x1]))
+            n_ok = min(w, (x1 - x0) - int(vx * (t + 1)) - 2)  # columns whose chains stay inside
+            got = out[:, y0:y1, x0:x0 + n_ok].cpu().numpy()
+            e = g1(got, ref[:, :, :n_ok], scale[:, :, :n_ok])
+            assert e <= G1_TOL, (t, x0, y0, e)
+    g.close()
+    torch.cuda.synchronize()
