@@ -60,6 +60,7 @@ def _load():
     lib.oracle_reset.argtypes = [ctypes.c_void_p]
     lib.oracle_frames.restype = ctypes.c_long
     lib.oracle_frames.argtypes = [ctypes.c_void_p]
+    lib.oracle_set_origin.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]
     lib.oracle_threads.restype = ctypes.c_int
     lib.oracle_threads.argtypes = []
     lib.oracle_step.restype = ctypes.c_int
@@ -100,7 +101,7 @@ class Oracle:
     """
 
     def __init__(self, width, height, d, lam=0.98, delta=1.0, var_floor=1e-6,
-                 wmode=W_INVVAR, interp=INTERP_BILINEAR):
+                 wmode=W_INVVAR, interp=INTERP_BILINEAR, origin=(0, 0)):
         self._lib = _load()
         self.W, self.H, self.d = int(width), int(height), int(d)
         self.lam, self.delta = float(lam), float(delta)
@@ -109,6 +110,9 @@ class Oracle:
         if not h:
             raise ValueError("oracle_create rejected the parameters")
         self._h = h
+        # a crop of a larger image: source positions are rounded in that
+        # image's coordinates (see oracle_set_origin)
+        self._lib.oracle_set_origin(h, int(origin[0]), int(origin[1]))
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -57,6 +57,7 @@ typedef struct oracle {
     double var_floor;  /* smallest variance turned into a weight */
     int wmode;
     int interp;
+    int ox, oy;        /* position of pixel (0, 0) in a larger image (crops) */
     long frames;       /* frames processed since creation or reset */
     /* Per-pixel state, pixel-major: P is d*d (full, row-major), beta 3*d. */
     double *P_cur, *beta_cur;
@@ -120,6 +121,13 @@ void oracle_reset(oracle *o)
 
 long oracle_frames(const oracle *o) { return o->frames; }
 
+/* Declares this image a crop of a larger one whose pixel (ox, oy) is this
+ * image's pixel (0, 0).  The source position j + v is then rounded to
+ * binary32 in the larger image's coordinates, exactly as for the full image,
+ * so a crop reproduces the full image's arithmetic bit for bit (pixels whose
+ * sources fall outside the crop restart, as at an image border). */
+void oracle_set_origin(oracle *o, int ox, int oy) { o->ox = ox; o->oy = oy; }
+
 /* Threads the per-row loop of oracle_step runs on. */
 int oracle_threads(void) { return omp_get_max_threads(); }
 
@@ -134,8 +142,10 @@ static int reproject(const oracle *o, int x, int y, double vx_in, double vy_in,
 {
     int d = o->d, W = o->W, H = o->H;
     if (!isfinite(vx_in) || !isfinite(vy_in)) return 0;
-    float sx = (float)x + (float)vx_in;
-    float sy = (float)y + (float)vy_in;
+    /* binary32 position in the coordinates of the (possibly larger) image;
+     * removing the integer origin again is exact */
+    float sx = ((float)(x + o->ox) + (float)vx_in) - (float)o->ox;
+    float sy = ((float)(y + o->oy) + (float)vy_in) - (float)o->oy;
     if (!(sx >= 0.0f && sx <= (float)(W - 1) && sy >= 0.0f && sy <= (float)(H - 1)))
         return 0;
 

@@ -47,7 +47,7 @@ int64_t plane_pitch(const wrls_params *p)
     return (n + a - 1) / a * a;
 }
 
-wrls::TileShape default_tile() { return wrls::TileShape{7, 256}; }
+wrls::TileShape default_tile() { return wrls::TileShape{7, 256, 0}; }
 
 }  // namespace
 
@@ -171,22 +171,27 @@ wrls_status wrls_set_hip_stream(wrls_stream *s, void *hip_stream)
     return WRLS_OK;
 }
 
-wrls_status wrls_set_tile(wrls_stream *s, int32_t tile_w_log2, int32_t block_threads)
+wrls_status wrls_set_tile(wrls_stream *s, int32_t tile_w_log2, int32_t block_threads,
+                          int32_t strip_tiles)
 {
     if (!s) return fail(WRLS_EINVAL, "stream handle is NULL");
     if (block_threads != 64 && block_threads != 128 && block_threads != 256)
         return fail(WRLS_EINVAL, "block_threads = %d not in {64, 128, 256}", block_threads);
     if (tile_w_log2 < 0 || (1 << tile_w_log2) > block_threads)
         return fail(WRLS_EINVAL, "tile width 2^%d exceeds %d threads", tile_w_log2, block_threads);
-    s->tile = wrls::TileShape{tile_w_log2, block_threads};
+    if (strip_tiles < 0) return fail(WRLS_EINVAL, "strip_tiles = %d < 0", strip_tiles);
+    s->tile = wrls::TileShape{tile_w_log2, block_threads, strip_tiles};
     return WRLS_OK;
 }
 
-wrls_status wrls_get_tile(const wrls_stream *s, int32_t *tile_w_log2, int32_t *block_threads)
+wrls_status wrls_get_tile(const wrls_stream *s, int32_t *tile_w_log2, int32_t *block_threads,
+                          int32_t *strip_tiles)
 {
-    if (!s || !tile_w_log2 || !block_threads) return fail(WRLS_EINVAL, "NULL argument");
+    if (!s || !tile_w_log2 || !block_threads || !strip_tiles)
+        return fail(WRLS_EINVAL, "NULL argument");
     *tile_w_log2 = s->tile.tw_log2;
     *block_threads = s->tile.block_threads;
+    *strip_tiles = s->tile.strip_w;
     return WRLS_OK;
 }
 

@@ -253,12 +253,36 @@ __device__ __forceinline__ void update_pixel(const FrameArgs &a, int x, int y)
     for (int c = 0; c < 3; c++) bstore(r_out, oj, (uint32_t)c * n * 4u, out[c]);
 }
 
+// Tile order: the image is cut into vertical strips of strip_w tiles (the
+// last strip may be narrower); tiles run strip by strip, and inside a strip
+// row by row.  A tile row of a strip re-reads the bottom source rows of the
+// tile row above it, so keeping strips narrow keeps that reuse inside L2
+// even when a full image row of state (up to 85 planes at 4K) would not fit.
+__device__ __forceinline__ void tile_coords(int L, int tiles_x, int tiles_y, int strip_w, int &tx,
+                                            int &ty)
+{
+    const int n_full = tiles_x / strip_w;
+    const int full = n_full * strip_w * tiles_y;
+    if (L < full) {
+        const int per = strip_w * tiles_y;
+        const int strip = L / per;
+        const int r = L - strip * per;
+        ty = r / strip_w;
+        tx = strip * strip_w + (r - ty * strip_w);
+    } else {
+        const int w_last = tiles_x - n_full * strip_w;
+        const int r = L - full;
+        ty = r / w_last;
+        tx = n_full * strip_w + (r - ty * w_last);
+    }
+}
+
 template <int D, typename InT>
 __global__ void __launch_bounds__(256) step_kernel(const FrameArgs a, const TileShape ts)
 {
     const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
-    const int tx = tile % a.tiles_x;
-    const int ty = tile / a.tiles_x;
+    int tx, ty;
+    tile_coords(tile, a.tiles_x, a.tiles_y, a.strip_w, tx, ty);
     const int tw_mask = (1 << ts.tw_log2) - 1;
     const int x = (tx << ts.tw_log2) + ((int)threadIdx.x & tw_mask);
     const int y = ty * (ts.block_threads >> ts.tw_log2) + ((int)threadIdx.x >> ts.tw_log2);
@@ -296,6 +320,14 @@ hipError_t launch_step_d(bool f16, const FrameArgs &a, TileShape ts, hipStream_t
     const int tiles_y = (a.H + th - 1) / th;
     FrameArgs b = a;
     b.tiles_x = tiles_x;
+    b.tiles_y = tiles_y;
+    int strip_w = ts.strip_w;
+    if (strip_w <= 0) {
+        // source rows of one strip tile row: tile width x (th + 1) rows x S planes
+        const int64_t per_tile = (int64_t)tw * 4 * (th + 1) * state_floats(D);
+        strip_w = (int)(kStripBytes / per_tile);
+    }
+    b.strip_w = strip_w < 1 ? 1 : (strip_w > tiles_x ? tiles_x : strip_w);
     const dim3 grid((unsigned)(tiles_x * tiles_y)), block((unsigned)ts.block_threads);
     if (f16)
         hipLaunchKernelGGL((step_kernel<D, _Float16>), grid, block, 0, st, b, ts);

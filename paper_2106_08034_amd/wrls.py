@@ -51,8 +51,9 @@ SIGNATURES = {
     "wrls_create_stream": (ctypes.c_int, [_P, _VP, ctypes.POINTER(_VP)]),
     "wrls_destroy": (ctypes.c_int, [_VP]),
     "wrls_set_hip_stream": (ctypes.c_int, [_VP, _VP]),
-    "wrls_set_tile": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32]),
-    "wrls_get_tile": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
+    "wrls_set_tile": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "wrls_get_tile": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(ctypes.c_int32)]),
     "wrls_reset": (ctypes.c_int, [_VP]),
     "wrls_frames": (ctypes.c_int64, [_VP]),
     "wrls_step": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP]),
@@ -138,14 +139,14 @@ def wrls_set_hip_stream(h: int, hip_stream: Optional[int]):
     _check(lib().wrls_set_hip_stream(h, hip_stream))
 
 
-def wrls_set_tile(h: int, tile_w_log2: int, block_threads: int):
-    _check(lib().wrls_set_tile(h, tile_w_log2, block_threads))
+def wrls_set_tile(h: int, tile_w_log2: int, block_threads: int, strip_tiles: int = 0):
+    _check(lib().wrls_set_tile(h, tile_w_log2, block_threads, strip_tiles))
 
 
-def wrls_get_tile(h: int) -> Tuple[int, int]:
-    a, b = ctypes.c_int32(), ctypes.c_int32()
-    _check(lib().wrls_get_tile(h, ctypes.byref(a), ctypes.byref(b)))
-    return a.value, b.value
+def wrls_get_tile(h: int) -> Tuple[int, int, int]:
+    a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().wrls_get_tile(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value
 
 
 def wrls_reset(h: int):
@@ -247,11 +248,11 @@ class Stream:
     def reset(self):
         wrls_reset(self.handle)
 
-    def set_tile(self, tile_w_log2: int, block_threads: int):
-        wrls_set_tile(self.handle, tile_w_log2, block_threads)
+    def set_tile(self, tile_w_log2: int, block_threads: int, strip_tiles: int = 0):
+        wrls_set_tile(self.handle, tile_w_log2, block_threads, strip_tiles)
 
     @property
-    def tile(self) -> Tuple[int, int]:
+    def tile(self) -> Tuple[int, int, int]:
         return wrls_get_tile(self.handle)
 
     def get_state(self) -> Tuple["object", "object"]:

@@ -218,7 +218,9 @@ def test_maximum_size_d10_sampled_windows():
     """The largest square image a d = 10 stream accepts (state copy just
     below 4 GiB), FP16 inputs, a sub-pixel pan.  A pixel's model depends only
     on the pixels its motion chain visits, so crops whose chains stay inside
-    them are run through small oracles and compared pixel by pixel."""
+    them are run through small oracles (placed at the crop's origin, so that
+    source positions round as in the full image) and compared pixel by
+    pixel."""
     import oracle
     import torch
     from paper_2106_08034_amd import wrls
@@ -232,7 +234,8 @@ def test_maximum_size_d10_sampled_windows():
     wins = [(0, 0), (side - 48, side - 6), (side // 2 + 5, side // 3), (side - 8 - int(vx * T) - 3, 7)]
     w, h = 40, 6
     crops = [(x0, y0, min(side, x0 + w + int(vx * T) + 3), y0 + h) for (x0, y0) in wins]
-    oracles = [oracle.Oracle(c[2] - c[0], c[3] - c[1], d) for c in crops]
+    # each crop's oracle rounds source positions in the full image's coordinates
+    oracles = [oracle.Oracle(c[2] - c[0], c[3] - c[1], d, origin=(c[0], c[1])) for c in crops]
     for t in range(T):
         f = src.next()
         out = g.step(to_dev(f.color), to_dev(f.feats), to_dev(f.var), to_dev(f.motion))

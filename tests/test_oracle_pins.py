@@ -367,3 +367,28 @@ def test_region_of_interest_matches_full_frame():
         o = part.step(ys[t], ps[t], var[t], motion[t], roi=rois[t])
     x0, y0, x1, y1 = win
     assert np.array_equal(o[:, y0:y1, x0:x1], outs[-1][:, y0:y1, x0:x1])
+
+
+def test_crop_with_origin_reproduces_full_image_bitwise():
+    """A crop declared at its origin rounds source positions like the full
+    image (binary32 rounding of x + v depends on |x|), so pixels whose
+    motion chains stay inside the crop match the full image bitwise."""
+    rng = np.random.default_rng(12)
+    T, H, W, d = 4, 6, 3000, 4
+    ps, ys, var = _inputs(rng, T, H, W, d)
+    motion = np.zeros((T, 2, H, W))
+    motion[:, 0] = 2.3
+    motion[:, 1] = rng.uniform(-0.4, 0.4, size=(T, H, W)) * 0  # rows stay independent
+    full = oracle.Oracle(W, H, d)
+    for t in range(T):
+        out_full = full.step(ys[t], ps[t], var[t], motion[t])
+    x0, x1 = 2900, 2960
+    crop = oracle.Oracle(x1 - x0, H, d, origin=(x0, 0))
+    local = oracle.Oracle(x1 - x0, H, d)
+    for t in range(T):
+        out_crop = crop.step(ys[t][:, :, x0:x1], ps[t][:, :, x0:x1], var[t][:, x0:x1], motion[t][:, :, x0:x1])
+        out_local = local.step(ys[t][:, :, x0:x1], ps[t][:, :, x0:x1], var[t][:, x0:x1], motion[t][:, :, x0:x1])
+    n_ok = (x1 - x0) - int(2.3 * T) - 2
+    assert np.array_equal(out_crop[:, :, :n_ok], out_full[:, :, x0:x0 + n_ok])
+    # without the origin, binary32 rounding of the source position differs
+    assert not np.array_equal(out_local[:, :, :n_ok], out_full[:, :, x0:x0 + n_ok])
