@@ -43,18 +43,13 @@ struct FrameArgs {
 
 // Launch shape of the per-frame kernel: a tile is (1 << tw_log2) pixels
 // wide and block_threads >> tw_log2 rows high; one thread per pixel.  Tiles
-// run in vertical strips of strip_w tiles (0: chosen from the state size so
-// that one tile row of a strip, with its source rows, fits well inside an
-// XCD's L2).
+// run in vertical strips of strip_w tiles (0: one strip, the full width).
 struct TileShape {
     int32_t tw_log2;
     int32_t block_threads;
     int32_t strip_w;
 };
 
-// Source rows of one band of a strip that should stay in L2 until the band
-// below reuses them (the MI355X L2 is 4 MiB per XCD).
-constexpr int64_t kStripBytes = 1 << 20;
 
 hipError_t launch_reset(float *state, int64_t pitch, int64_t npix, int d, float p0,
                         hipStream_t st);

@@ -255,9 +255,10 @@ __device__ __forceinline__ void update_pixel(const FrameArgs &a, int x, int y)
 
 // Tile order: the image is cut into vertical strips of strip_w tiles (the
 // last strip may be narrower); tiles run strip by strip, and inside a strip
-// row by row.  A tile row of a strip re-reads the bottom source rows of the
-// tile row above it, so keeping strips narrow keeps that reuse inside L2
-// even when a full image row of state (up to 85 planes at 4K) would not fit.
+// row by row.  A tile row re-reads the bottom source rows of the tile row
+// above it; narrow strips keep that reuse inside L2 (4K at d = 10: reads
+// 1.14x instead of 1.48x the algorithmic bytes) but measured slower than
+// the full width, which is the default -- the autotuner may pick a strip.
 __device__ __forceinline__ void tile_coords(int L, int tiles_x, int tiles_y, int strip_w, int &tx,
                                             int &ty)
 {
@@ -321,13 +322,8 @@ hipError_t launch_step_d(bool f16, const FrameArgs &a, TileShape ts, hipStream_t
     FrameArgs b = a;
     b.tiles_x = tiles_x;
     b.tiles_y = tiles_y;
-    int strip_w = ts.strip_w;
-    if (strip_w <= 0) {
-        // source rows of one strip tile row: tile width x (th + 1) rows x S planes
-        const int64_t per_tile = (int64_t)tw * 4 * (th + 1) * state_floats(D);
-        strip_w = (int)(kStripBytes / per_tile);
-    }
-    b.strip_w = strip_w < 1 ? 1 : (strip_w > tiles_x ? tiles_x : strip_w);
+    const int strip_w = ts.strip_w <= 0 ? tiles_x : ts.strip_w;
+    b.strip_w = strip_w > tiles_x ? tiles_x : strip_w;
     const dim3 grid((unsigned)(tiles_x * tiles_y)), block((unsigned)ts.block_threads);
     if (f16)
         hipLaunchKernelGGL((step_kernel<D, _Float16>), grid, block, 0, st, b, ts);
