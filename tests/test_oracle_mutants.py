@@ -23,7 +23,10 @@ MUTANTS = {
     "eq11_forgetting": ("(P[i * d + k] - q[i] * pP[k]) / lambda", "(P[i * d + k] - q[i] * pP[k]) * lambda"),
     "weight_is_std": ("return 1.0 / v;", "return 1.0 / sqrt(v);"),
     "prior_inverted": ("(i == k) ? 1.0 / o->delta : 0.0", "(i == k) ? o->delta : 0.0"),
-    "reproject_sign": ("float sx = (float)x + (float)vx_in;", "float sx = (float)x - (float)vx_in;"),
+    "reproject_sign": ("float sx = ((float)(x + o->ox) + (float)vx_in) - (float)o->ox;",
+                       "float sx = ((float)(x + o->ox) - (float)vx_in) - (float)o->ox;"),
+    "origin_ignored": ("float sy = ((float)(y + o->oy) + (float)vy_in) - (float)o->oy;",
+                       "float sy = (float)y + (float)vy_in;"),
     "bilinear_weights_swapped": ("double w10 = fx * (1.0 - fy);\n    double w01 = (1.0 - fx) * fy;",
                                  "double w10 = (1.0 - fx) * fy;\n    double w01 = fx * (1.0 - fy);"),
     "bilinear_tap_transposed": ("size_t s00 = (size_t)y0 * W + x0, s10 = (size_t)y0 * W + x1;",

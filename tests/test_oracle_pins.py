@@ -369,26 +369,35 @@ def test_region_of_interest_matches_full_frame():
     assert np.array_equal(o[:, y0:y1, x0:x1], outs[-1][:, y0:y1, x0:x1])
 
 
-def test_crop_with_origin_reproduces_full_image_bitwise():
+@pytest.mark.parametrize("axis", [0, 1])
+def test_crop_with_origin_reproduces_full_image_bitwise(axis):
     """A crop declared at its origin rounds source positions like the full
     image (binary32 rounding of x + v depends on |x|), so pixels whose
-    motion chains stay inside the crop match the full image bitwise."""
+    motion chains stay inside the crop match the full image bitwise.
+    axis 0: a horizontal pan across x ~ 2900; axis 1: a vertical pan across
+    y ~ 2900."""
     rng = np.random.default_rng(12)
-    T, H, W, d = 4, 6, 3000, 4
+    T, d, long_, short = 4, 4, 3000, 6
+    H, W = (short, long_) if axis == 0 else (long_, short)
     ps, ys, var = _inputs(rng, T, H, W, d)
     motion = np.zeros((T, 2, H, W))
-    motion[:, 0] = 2.3
-    motion[:, 1] = rng.uniform(-0.4, 0.4, size=(T, H, W)) * 0  # rows stay independent
+    motion[:, axis] = 2.3
     full = oracle.Oracle(W, H, d)
     for t in range(T):
         out_full = full.step(ys[t], ps[t], var[t], motion[t])
-    x0, x1 = 2900, 2960
-    crop = oracle.Oracle(x1 - x0, H, d, origin=(x0, 0))
-    local = oracle.Oracle(x1 - x0, H, d)
+    a0, a1 = 2900, 2960
+    sl = (slice(None), slice(None), slice(a0, a1)) if axis == 0 else (slice(None), slice(a0, a1), slice(None))
+    sl2 = sl[1:]
+    cw, ch = (a1 - a0, H) if axis == 0 else (W, a1 - a0)
+    crop = oracle.Oracle(cw, ch, d, origin=(a0, 0) if axis == 0 else (0, a0))
+    local = oracle.Oracle(cw, ch, d)
     for t in range(T):
-        out_crop = crop.step(ys[t][:, :, x0:x1], ps[t][:, :, x0:x1], var[t][:, x0:x1], motion[t][:, :, x0:x1])
-        out_local = local.step(ys[t][:, :, x0:x1], ps[t][:, :, x0:x1], var[t][:, x0:x1], motion[t][:, :, x0:x1])
-    n_ok = (x1 - x0) - int(2.3 * T) - 2
-    assert np.array_equal(out_crop[:, :, :n_ok], out_full[:, :, x0:x0 + n_ok])
+        args = (ys[t][sl], ps[t][sl], var[t][sl2], motion[t][sl])
+        out_crop = crop.step(*args)
+        out_local = local.step(*args)
+    n_ok = (a1 - a0) - int(2.3 * T) - 2
+    keep = (slice(None), slice(None), slice(0, n_ok)) if axis == 0 else (slice(None), slice(0, n_ok), slice(None))
+    ref = out_full[sl][keep]
+    assert np.array_equal(out_crop[keep], ref)
     # without the origin, binary32 rounding of the source position differs
-    assert not np.array_equal(out_local[:, :, :n_ok], out_full[:, :, x0:x0 + n_ok])
+    assert not np.array_equal(out_local[keep], ref)
