@@ -114,8 +114,16 @@ size_t wrls_stream_device_bytes(const wrls_params *p);
  * later work on that HIP stream. */
 wrls_status wrls_create_stream(const wrls_params *p, void *hip_stream, wrls_stream **out);
 
-/* Waits for the handle's HIP stream, frees its state and the handle.  A null
- * handle is accepted and ignored. */
+/* Like wrls_create_stream, but the state lives in caller-owned device
+ * memory: device_mem (256-byte aligned) of at least
+ * wrls_stream_device_bytes(p) bytes, which must stay valid until
+ * wrls_destroy; the library never frees it.  For servers that admit streams
+ * into a preallocated HBM arena without allocating per stream. */
+wrls_status wrls_create_stream_in(const wrls_params *p, void *device_mem, size_t bytes,
+                                  void *hip_stream, wrls_stream **out);
+
+/* Waits for the handle's HIP stream, frees its state (unless caller-owned)
+ * and the handle.  A null handle is accepted and ignored. */
 wrls_status wrls_destroy(wrls_stream *s);
 
 /* Moves the handle's later work to another HIP stream (a hipStream_t). */
@@ -165,6 +173,62 @@ wrls_status wrls_get_state(const wrls_stream *s, float *P_packed, float *beta);
  * frame counter; with frames > 0 the next step reprojects from this state. */
 wrls_status wrls_set_state(wrls_stream *s, const float *P_packed, const float *beta,
                            int64_t frames);
+
+/* ---- Batched steps: many streams, one persistent launch ----------------
+ *
+ * A batch advances several streams by one frame each with ONE launch of a
+ * persistent kernel whose grid is fixed (compute units x workgroups per CU):
+ * the workgroups walk the concatenated tiles of all the frames.  The frames'
+ * pointers go through a device-resident table that is refilled every step,
+ * so the step can be captured once as a HIP graph and replayed for any
+ * composition of streams (up to max_streams).  Each stream's result is
+ * bitwise the same as with wrls_step. */
+
+/* Device pointers of one stream's frame; layouts as in wrls_step. */
+typedef struct {
+    const void *color;
+    const void *features;
+    const float *variance;
+    const float *motion;
+    float *out;
+} wrls_frame;
+
+typedef struct wrls_batch wrls_batch;  /* opaque, owned by the library */
+
+/* Largest number of streams one batched step accepts. */
+#define WRLS_MAX_BATCH 64
+
+/* Creates a batch context for streams of predictor length d and input type
+ * in_dtype, whose steps are enqueued on hip_stream (a hipStream_t; NULL:
+ * the batch creates and owns a stream).  Allocates the device table (twice,
+ * so one step can be prepared while the previous one runs) and pinned host
+ * staging.  Streams stepped through the batch must be ordered with the
+ * batch's HIP stream (create them on it, or synchronise). */
+wrls_status wrls_batch_create(int32_t max_streams, int32_t d, int32_t in_dtype, void *hip_stream,
+                              wrls_batch **out);
+
+/* Waits for the batch's HIP stream and frees the batch (not the streams). */
+wrls_status wrls_batch_destroy(wrls_batch *b);
+
+/* The batch's HIP stream (a hipStream_t). */
+void *wrls_batch_hip_stream(const wrls_batch *b);
+
+/* Launch shape: tile as in wrls_set_tile, and workgroups per compute unit
+ * of the persistent grid (1..16; 0: as many as are resident at once, the
+ * default).  Replaces any captured graph. */
+wrls_status wrls_batch_set_tile(wrls_batch *b, int32_t tile_w_log2, int32_t block_threads,
+                                int32_t blocks_per_cu);
+
+/* 1: replay a captured HIP graph per step (captured on first use);
+ * 0: plain enqueue (copy of the table + launch).  Default 1. */
+wrls_status wrls_batch_use_graph(wrls_batch *b, int32_t enable);
+
+/* One frame for each of streams[0..n-1] (distinct handles, same d and
+ * in_dtype as the batch, n <= max_streams); frames[i] belongs to
+ * streams[i].  Stream-ordered on the batch's HIP stream; returns without
+ * synchronising. */
+wrls_status wrls_batch_step(wrls_batch *b, int32_t n, wrls_stream *const *streams,
+                            const wrls_frame *frames);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char *wrls_last_error(void);

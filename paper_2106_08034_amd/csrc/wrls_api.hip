@@ -15,6 +15,7 @@ struct wrls_stream {
     hipStream_t st;
     float *state[2];  // previous / current frame, S planes of `pitch` floats each
     void *alloc;      // the single device allocation holding both copies
+    bool owns_alloc;  // false: caller-owned memory (wrls_create_stream_in)
     int64_t pitch;
     int cur;          // index of the state holding the latest frame
     int64_t frames;
@@ -118,12 +119,12 @@ size_t wrls_stream_device_bytes(const wrls_params *p)
     return 2 * (size_t)wrls::state_floats(p->d) * sizeof(float) * (size_t)plane_pitch(p);
 }
 
-wrls_status wrls_create_stream(const wrls_params *p, void *hip_stream, wrls_stream **out)
+namespace {
+
+// Common part of the two constructors: mem holds both state copies.
+wrls_status init_stream(const wrls_params *p, void *hip_stream, void *mem, bool owns,
+                        wrls_stream **out)
 {
-    if (!out) return fail(WRLS_EINVAL, "out is NULL");
-    *out = nullptr;
-    wrls_status rc = wrls_params_validate(p);
-    if (rc != WRLS_OK) return rc;
     wrls_stream *s = new (std::nothrow) wrls_stream();
     if (!s) return fail(WRLS_ENOMEM, "host allocation of the handle failed");
     s->prm = *p;
@@ -132,20 +133,14 @@ wrls_status wrls_create_stream(const wrls_params *p, void *hip_stream, wrls_stre
     s->cur = 0;
     s->frames = 0;
     s->tile = default_tile();
-    const size_t one = (size_t)wrls::state_floats(p->d) * (size_t)s->pitch;
-    void *mem = nullptr;
-    hipError_t e = hipMalloc(&mem, 2 * one * sizeof(float));
-    if (e != hipSuccess) {
-        delete s;
-        return hip_fail(e, "hipMalloc of the stream state");
-    }
     s->alloc = mem;
+    s->owns_alloc = owns;
+    const size_t one = (size_t)wrls::state_floats(p->d) * (size_t)s->pitch;
     s->state[0] = static_cast<float *>(mem);
     s->state[1] = s->state[0] + one;
     const int64_t npix = (int64_t)p->width * p->height;
-    e = wrls::launch_reset(s->state[0], s->pitch, npix, p->d, 1.0f / p->delta, s->st);
+    hipError_t e = wrls::launch_reset(s->state[0], s->pitch, npix, p->d, 1.0f / p->delta, s->st);
     if (e != hipSuccess) {
-        (void)hipFree(mem);
         delete s;
         return hip_fail(e, "state initialisation");
     }
@@ -153,11 +148,43 @@ wrls_status wrls_create_stream(const wrls_params *p, void *hip_stream, wrls_stre
     return WRLS_OK;
 }
 
+}  // namespace
+
+wrls_status wrls_create_stream(const wrls_params *p, void *hip_stream, wrls_stream **out)
+{
+    if (!out) return fail(WRLS_EINVAL, "out is NULL");
+    *out = nullptr;
+    wrls_status rc = wrls_params_validate(p);
+    if (rc != WRLS_OK) return rc;
+    void *mem = nullptr;
+    hipError_t e = hipMalloc(&mem, wrls_stream_device_bytes(p));
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc of the stream state");
+    rc = init_stream(p, hip_stream, mem, true, out);
+    if (rc != WRLS_OK) (void)hipFree(mem);
+    return rc;
+}
+
+wrls_status wrls_create_stream_in(const wrls_params *p, void *device_mem, size_t bytes,
+                                  void *hip_stream, wrls_stream **out)
+{
+    if (!out) return fail(WRLS_EINVAL, "out is NULL");
+    *out = nullptr;
+    wrls_status rc = wrls_params_validate(p);
+    if (rc != WRLS_OK) return rc;
+    if (!device_mem) return fail(WRLS_EINVAL, "device_mem is NULL");
+    if (((uintptr_t)device_mem & 255) != 0)
+        return fail(WRLS_EINVAL, "device_mem is not 256-byte aligned");
+    const size_t need = wrls_stream_device_bytes(p);
+    if (bytes < need)
+        return fail(WRLS_EINVAL, "device_mem holds %zu bytes, the stream needs %zu", bytes, need);
+    return init_stream(p, hip_stream, device_mem, false, out);
+}
+
 wrls_status wrls_destroy(wrls_stream *s)
 {
     if (!s) return WRLS_OK;
     hipError_t e1 = hipStreamSynchronize(s->st);
-    hipError_t e2 = hipFree(s->alloc);
+    hipError_t e2 = s->owns_alloc ? hipFree(s->alloc) : hipSuccess;
     delete s;
     if (e1 != hipSuccess) return hip_fail(e1, "hipStreamSynchronize in destroy");
     if (e2 != hipSuccess) return hip_fail(e2, "hipFree in destroy");
@@ -208,38 +235,59 @@ wrls_status wrls_reset(wrls_stream *s)
 
 int64_t wrls_frames(const wrls_stream *s) { return s ? s->frames : -1; }
 
-wrls_status wrls_step(wrls_stream *s, const void *color, const void *features,
-                      const float *variance, const float *motion, float *out)
+namespace {
+
+// Checks one frame's pointers and fills the kernel arguments of the next
+// step of s (reads state[cur], writes state[1 - cur]).
+wrls_status frame_args(const wrls_stream *s, const void *color, const void *features,
+                       const float *variance, const float *motion, float *out,
+                       wrls::FrameArgs *a)
 {
-    if (!s) return fail(WRLS_EINVAL, "stream handle is NULL");
     const wrls_params &p = s->prm;
     if (!color) return fail(WRLS_EINVAL, "color is NULL");
     if (!out) return fail(WRLS_EINVAL, "out is NULL");
     if (p.d > 1 && !features) return fail(WRLS_EINVAL, "features is NULL with d = %d", p.d);
     if (p.weight_mode == WRLS_W_INVVAR && !variance)
         return fail(WRLS_EINVAL, "variance is NULL with inverse-variance weights");
-    wrls::FrameArgs a{};
-    a.color = color;
-    a.feats = features;
-    a.var = p.weight_mode == WRLS_W_INVVAR ? variance : nullptr;
-    a.motion = motion;
-    a.out = out;
-    a.state_in = s->state[s->cur];
-    a.state_out = s->state[1 - s->cur];
-    a.W = p.width;
-    a.H = p.height;
-    a.pitch = s->pitch;
-    a.lambda = p.lambda;
-    a.inv_lambda = 1.0f / p.lambda;
-    a.p0 = 1.0f / p.delta;
-    a.var_floor = p.var_floor;
-    a.fresh = s->frames == 0;
-    a.unit_weight = p.weight_mode == WRLS_W_ONE;
-    a.nearest = p.interp == WRLS_INTERP_NEAREST;
-    hipError_t e = wrls::launch_step(p.d, p.in_dtype == WRLS_F16, a, s->tile, s->st);
-    if (e != hipSuccess) return hip_fail(e, "step launch");
+    *a = wrls::FrameArgs{};
+    a->color = color;
+    a->feats = features;
+    a->var = p.weight_mode == WRLS_W_INVVAR ? variance : nullptr;
+    a->motion = motion;
+    a->out = out;
+    a->state_in = s->state[s->cur];
+    a->state_out = s->state[1 - s->cur];
+    a->W = p.width;
+    a->H = p.height;
+    a->pitch = s->pitch;
+    a->lambda = p.lambda;
+    a->inv_lambda = 1.0f / p.lambda;
+    a->p0 = 1.0f / p.delta;
+    a->var_floor = p.var_floor;
+    a->fresh = s->frames == 0;
+    a->unit_weight = p.weight_mode == WRLS_W_ONE;
+    a->nearest = p.interp == WRLS_INTERP_NEAREST;
+    return WRLS_OK;
+}
+
+void advance(wrls_stream *s)
+{
     s->cur = 1 - s->cur;
     s->frames++;
+}
+
+}  // namespace
+
+wrls_status wrls_step(wrls_stream *s, const void *color, const void *features,
+                      const float *variance, const float *motion, float *out)
+{
+    if (!s) return fail(WRLS_EINVAL, "stream handle is NULL");
+    wrls::FrameArgs a;
+    wrls_status rc = frame_args(s, color, features, variance, motion, out, &a);
+    if (rc != WRLS_OK) return rc;
+    hipError_t e = wrls::launch_step(s->prm.d, s->prm.in_dtype == WRLS_F16, a, s->tile, s->st);
+    if (e != hipSuccess) return hip_fail(e, "step launch");
+    advance(s);
     return WRLS_OK;
 }
 
@@ -283,6 +331,224 @@ wrls_status wrls_set_state(wrls_stream *s, const float *P_packed, const float *b
                          hipMemcpyDeviceToDevice, s->st);
     if (e != hipSuccess) return hip_fail(e, "state import (beta)");
     s->frames = frames;
+    return WRLS_OK;
+}
+
+
+// ---- batched steps -------------------------------------------------------
+
+struct wrls_batch {
+    int32_t max_streams, d, in_dtype;
+    hipStream_t st;
+    bool owns_st;
+    wrls::BatchTable *dev_tab[2];   // device tables, used alternately
+    wrls::BatchTable *host_tab[2];  // pinned staging of each
+    hipEvent_t done[2];             // recorded after the step that used slot i
+    bool pending[2];
+    int slot;
+    wrls::TileShape tile;
+    int32_t blocks_per_cu;
+    int32_t cu_count;
+    bool use_graph;
+    hipGraphExec_t exec[2];
+};
+
+namespace {
+
+void drop_graphs(wrls_batch *b)
+{
+    for (int i = 0; i < 2; i++)
+        if (b->exec[i]) {
+            (void)hipGraphExecDestroy(b->exec[i]);
+            b->exec[i] = nullptr;
+        }
+}
+
+// Workgroups per CU of the persistent grid by default: as many as are
+// resident at once (a larger grid would leave a tail of workgroups running
+// after the others, a smaller one idle slots).
+hipError_t default_blocks_per_cu(const wrls_batch *b, int32_t block_threads, int32_t *out)
+{
+    int n = 0;
+    hipError_t e = wrls::batched_blocks_per_cu(b->d, b->in_dtype == WRLS_F16, block_threads, &n);
+    if (e == hipSuccess) *out = n < 1 ? 1 : n;
+    return e;
+}
+
+int32_t batch_grid(const wrls_batch *b) { return b->cu_count * b->blocks_per_cu; }
+
+// Enqueues the table copy and the persistent launch of slot i on b->st.
+hipError_t enqueue_step(wrls_batch *b, int i)
+{
+    hipError_t e = hipMemcpyAsync(b->dev_tab[i], b->host_tab[i], sizeof(wrls::BatchTable),
+                                  hipMemcpyHostToDevice, b->st);
+    if (e != hipSuccess) return e;
+    return wrls::launch_step_batched(b->d, b->in_dtype == WRLS_F16, b->dev_tab[i], batch_grid(b),
+                                     b->tile.block_threads, b->st);
+}
+
+}  // namespace
+
+wrls_status wrls_batch_create(int32_t max_streams, int32_t d, int32_t in_dtype, void *hip_stream,
+                              wrls_batch **out)
+{
+    if (!out) return fail(WRLS_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (max_streams < 1 || max_streams > WRLS_MAX_BATCH)
+        return fail(WRLS_EINVAL, "max_streams = %d outside [1, %d]", max_streams, WRLS_MAX_BATCH);
+    if (d < 1 || d > WRLS_MAX_D) return fail(WRLS_EUNSUPPORTED, "d = %d outside [1, %d]", d, WRLS_MAX_D);
+    if (in_dtype != WRLS_F32 && in_dtype != WRLS_F16)
+        return fail(WRLS_EINVAL, "in_dtype = %d unknown", in_dtype);
+    wrls_batch *b = new (std::nothrow) wrls_batch();
+    if (!b) return fail(WRLS_ENOMEM, "host allocation of the batch failed");
+    b->max_streams = max_streams;
+    b->d = d;
+    b->in_dtype = in_dtype;
+    b->tile = default_tile();
+    b->use_graph = true;
+    hipError_t e = default_blocks_per_cu(b, b->tile.block_threads, &b->blocks_per_cu);
+    int dev = 0;
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&b->cu_count, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess && !hip_stream) {
+        e = hipStreamCreate(&b->st);
+        b->owns_st = e == hipSuccess;
+    } else {
+        b->st = static_cast<hipStream_t>(hip_stream);
+    }
+    for (int i = 0; i < 2 && e == hipSuccess; i++) {
+        e = hipMalloc(reinterpret_cast<void **>(&b->dev_tab[i]), sizeof(wrls::BatchTable));
+        if (e == hipSuccess)
+            e = hipHostMalloc(reinterpret_cast<void **>(&b->host_tab[i]), sizeof(wrls::BatchTable),
+                              hipHostMallocDefault);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done[i], hipEventDisableTiming);
+    }
+    if (e != hipSuccess) {
+        wrls_status rc = hip_fail(e, "batch creation");
+        wrls_batch_destroy(b);
+        return rc;
+    }
+    *out = b;
+    return WRLS_OK;
+}
+
+wrls_status wrls_batch_destroy(wrls_batch *b)
+{
+    if (!b) return WRLS_OK;
+    hipError_t e = hipStreamSynchronize(b->st);
+    drop_graphs(b);
+    for (int i = 0; i < 2; i++) {
+        if (b->dev_tab[i]) (void)hipFree(b->dev_tab[i]);
+        if (b->host_tab[i]) (void)hipHostFree(b->host_tab[i]);
+        if (b->done[i]) (void)hipEventDestroy(b->done[i]);
+    }
+    if (b->owns_st) (void)hipStreamDestroy(b->st);
+    delete b;
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize in batch destroy");
+    return WRLS_OK;
+}
+
+void *wrls_batch_hip_stream(const wrls_batch *b) { return b ? static_cast<void *>(b->st) : nullptr; }
+
+wrls_status wrls_batch_set_tile(wrls_batch *b, int32_t tile_w_log2, int32_t block_threads,
+                                int32_t blocks_per_cu)
+{
+    if (!b) return fail(WRLS_EINVAL, "batch handle is NULL");
+    if (block_threads != 64 && block_threads != 128 && block_threads != 256)
+        return fail(WRLS_EINVAL, "block_threads = %d not in {64, 128, 256}", block_threads);
+    if (tile_w_log2 < 0 || (1 << tile_w_log2) > block_threads)
+        return fail(WRLS_EINVAL, "tile width 2^%d exceeds %d threads", tile_w_log2, block_threads);
+    if (blocks_per_cu < 0 || blocks_per_cu > 16)
+        return fail(WRLS_EINVAL, "blocks_per_cu = %d outside [0, 16]", blocks_per_cu);
+    hipError_t e = hipSuccess;
+    if (blocks_per_cu == 0) {
+        e = default_blocks_per_cu(b, block_threads, &blocks_per_cu);
+        if (e != hipSuccess) return hip_fail(e, "occupancy query");
+    }
+    e = hipStreamSynchronize(b->st);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize in batch_set_tile");
+    drop_graphs(b);
+    b->tile = wrls::TileShape{tile_w_log2, block_threads, 0};
+    b->blocks_per_cu = blocks_per_cu;
+    return WRLS_OK;
+}
+
+wrls_status wrls_batch_use_graph(wrls_batch *b, int32_t enable)
+{
+    if (!b) return fail(WRLS_EINVAL, "batch handle is NULL");
+    b->use_graph = enable != 0;
+    return WRLS_OK;
+}
+
+wrls_status wrls_batch_step(wrls_batch *b, int32_t n, wrls_stream *const *streams,
+                            const wrls_frame *frames)
+{
+    if (!b) return fail(WRLS_EINVAL, "batch handle is NULL");
+    if (n < 0 || n > b->max_streams)
+        return fail(WRLS_EINVAL, "n = %d outside [0, %d]", n, b->max_streams);
+    if (n > 0 && (!streams || !frames)) return fail(WRLS_EINVAL, "streams or frames is NULL");
+    for (int i = 0; i < n; i++) {
+        const wrls_stream *s = streams[i];
+        if (!s) return fail(WRLS_EINVAL, "streams[%d] is NULL", i);
+        if (s->prm.d != b->d || s->prm.in_dtype != b->in_dtype)
+            return fail(WRLS_EINVAL, "streams[%d] has d = %d, dtype %d; the batch takes d = %d, dtype %d",
+                        i, s->prm.d, s->prm.in_dtype, b->d, b->in_dtype);
+        for (int k = 0; k < i; k++)
+            if (streams[k] == s) return fail(WRLS_EINVAL, "stream appears twice (%d and %d)", k, i);
+    }
+    const int i = b->slot;
+    // the staging buffer of this slot was last read by the step two calls ago
+    if (b->pending[i]) {
+        hipError_t e = hipEventSynchronize(b->done[i]);
+        if (e != hipSuccess) return hip_fail(e, "waiting for the batch table");
+        b->pending[i] = false;
+    }
+    wrls::BatchTable *t = b->host_tab[i];
+    t->n = n;
+    t->tile = b->tile;
+    t->prefix[0] = 0;
+    const int tw = 1 << b->tile.tw_log2;
+    const int th = b->tile.block_threads >> b->tile.tw_log2;
+    for (int k = 0; k < n; k++) {
+        const wrls_frame &f = frames[k];
+        wrls_status rc = frame_args(streams[k], f.color, f.features, f.variance, f.motion, f.out,
+                                    &t->frame[k]);
+        if (rc != WRLS_OK) {
+            char msg[sizeof g_err];
+            std::snprintf(msg, sizeof msg, "%s", g_err);
+            return fail(rc, "frames[%d]: %s", k, msg);
+        }
+        wrls::FrameArgs &a = t->frame[k];
+        a.tiles_x = (a.W + tw - 1) / tw;
+        a.tiles_y = (a.H + th - 1) / th;
+        a.strip_w = a.tiles_x;
+        t->prefix[k + 1] = t->prefix[k] + a.tiles_x * a.tiles_y;
+    }
+    t->total_tiles = t->prefix[n];
+    hipError_t e = hipSuccess;
+    if (b->use_graph) {
+        if (!b->exec[i]) {
+            hipGraph_t g = nullptr;
+            e = hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                hipError_t e2 = enqueue_step(b, i);
+                e = hipStreamEndCapture(b->st, &g);
+                if (e == hipSuccess) e = e2;
+            }
+            if (e == hipSuccess) e = hipGraphInstantiate(&b->exec[i], g, nullptr, nullptr, 0);
+            if (g) (void)hipGraphDestroy(g);
+            if (e != hipSuccess) return hip_fail(e, "batch graph capture");
+        }
+        e = hipGraphLaunch(b->exec[i], b->st);
+    } else {
+        e = enqueue_step(b, i);
+    }
+    if (e != hipSuccess) return hip_fail(e, "batch step");
+    e = hipEventRecord(b->done[i], b->st);
+    if (e != hipSuccess) return hip_fail(e, "batch event");
+    b->pending[i] = true;
+    b->slot = 1 - i;
+    for (int k = 0; k < n; k++) advance(streams[k]);
     return WRLS_OK;
 }
 

@@ -51,8 +51,27 @@ struct TileShape {
 };
 
 
+// Device-resident description of one batched step (rewritten every step):
+// the frames of up to kMaxBatch streams, all with the same d and input type
+// and one tile shape, and the prefix sums of their tile counts.
+constexpr int kMaxBatch = 64;
+struct BatchTable {
+    int32_t n;                  // frames in this step
+    int32_t total_tiles;        // prefix[n]
+    TileShape tile;             // strip_w unused: each image runs row by row
+    int32_t prefix[kMaxBatch + 1];
+    FrameArgs frame[kMaxBatch];
+};
+
 hipError_t launch_reset(float *state, int64_t pitch, int64_t npix, int d, float p0,
                         hipStream_t st);
 hipError_t launch_step(int d, bool f16, const FrameArgs &a, TileShape ts, hipStream_t st);
+// One persistent launch of `grid` workgroups of tab->tile.block_threads
+// threads over every tile of every frame in the device table `tab`.
+hipError_t launch_step_batched(int d, bool f16, const BatchTable *tab, int32_t grid,
+                               int32_t block_threads, hipStream_t st);
+// Workgroups of block_threads threads of the batched kernel that fit on one
+// compute unit at once (the persistent grid is this times the CU count).
+hipError_t batched_blocks_per_cu(int d, bool f16, int32_t block_threads, int *blocks_per_cu);
 
 }  // namespace wrls

@@ -332,6 +332,64 @@ hipError_t launch_step_d(bool f16, const FrameArgs &a, TileShape ts, hipStream_t
     return hipGetLastError();
 }
 
+// Batched persistent step: a fixed grid walks the concatenated tiles of all
+// frames of the table.  Workgroup b (after the XCD remap) owns the contiguous
+// tile range [b T / G, (b + 1) T / G), so each XCD sweeps one run of
+// neighbouring tiles; tiles have equal cost, so equal ranges balance.  The
+// grid does not depend on the frames, so one captured graph serves every
+// batch composition; workgroups with an empty range exit at once.
+// The loop bookkeeping costs the batched kernel ~10 registers over the
+// per-frame kernel; the occupancy hint keeps d <= 8 at 5 waves per SIMD
+// (94 registers, no spills), as the per-frame kernel; d = 10 spills at 5.
+template <int D, typename InT>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(D <= 8 ? 5 : 4)))
+batch_kernel(const BatchTable *__restrict__ tab)
+{
+    const int G = (int)gridDim.x;
+    const int b = xcd_tile((int)blockIdx.x, G);
+    const int total = tab->total_tiles;
+    const int t0 = (int)((int64_t)total * b / G);
+    const int t1 = (int)((int64_t)total * (b + 1) / G);
+    const int tw_log2 = tab->tile.tw_log2;
+    const int th = tab->tile.block_threads >> tw_log2;
+    const int lx = (int)threadIdx.x & ((1 << tw_log2) - 1);
+    const int ly = (int)threadIdx.x >> tw_log2;
+    int f = 0;
+    for (int t = t0; t < t1; t++) {
+        while (t >= tab->prefix[f + 1]) f++;
+        const FrameArgs a = tab->frame[f];
+        const int local = t - tab->prefix[f];
+        const int ty = local / a.tiles_x;
+        const int tx = local - ty * a.tiles_x;
+        const int x = (tx << tw_log2) + lx;
+        const int y = ty * th + ly;
+        if (x < a.W && y < a.H) update_pixel<D, InT>(a, x, y);
+    }
+}
+
+template <int D>
+hipError_t occupancy_batched_d(bool f16, int32_t block_threads, int *blocks_per_cu)
+{
+    if (f16)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            blocks_per_cu, reinterpret_cast<const void *>(&batch_kernel<D, _Float16>), block_threads, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        blocks_per_cu, reinterpret_cast<const void *>(&batch_kernel<D, float>), block_threads, 0);
+}
+
+template <int D>
+hipError_t launch_batched_d(bool f16, const BatchTable *tab, int32_t grid, int32_t block_threads,
+                            hipStream_t st)
+{
+    if (f16)
+        hipLaunchKernelGGL((batch_kernel<D, _Float16>), dim3((unsigned)grid),
+                           dim3((unsigned)block_threads), 0, st, tab);
+    else
+        hipLaunchKernelGGL((batch_kernel<D, float>), dim3((unsigned)grid),
+                           dim3((unsigned)block_threads), 0, st, tab);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_reset(float *state, int64_t pitch, int64_t npix, int d, float p0,
@@ -359,6 +417,41 @@ hipError_t launch_step(int d, bool f16, const FrameArgs &a, TileShape ts, hipStr
     case 8: return launch_step_d<8>(f16, a, ts, st);
     case 9: return launch_step_d<9>(f16, a, ts, st);
     case 10: return launch_step_d<10>(f16, a, ts, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_step_batched(int d, bool f16, const BatchTable *tab, int32_t grid,
+                               int32_t block_threads, hipStream_t st)
+{
+    switch (d) {
+    case 1: return launch_batched_d<1>(f16, tab, grid, block_threads, st);
+    case 2: return launch_batched_d<2>(f16, tab, grid, block_threads, st);
+    case 3: return launch_batched_d<3>(f16, tab, grid, block_threads, st);
+    case 4: return launch_batched_d<4>(f16, tab, grid, block_threads, st);
+    case 5: return launch_batched_d<5>(f16, tab, grid, block_threads, st);
+    case 6: return launch_batched_d<6>(f16, tab, grid, block_threads, st);
+    case 7: return launch_batched_d<7>(f16, tab, grid, block_threads, st);
+    case 8: return launch_batched_d<8>(f16, tab, grid, block_threads, st);
+    case 9: return launch_batched_d<9>(f16, tab, grid, block_threads, st);
+    case 10: return launch_batched_d<10>(f16, tab, grid, block_threads, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t batched_blocks_per_cu(int d, bool f16, int32_t block_threads, int *blocks_per_cu)
+{
+    switch (d) {
+    case 1: return occupancy_batched_d<1>(f16, block_threads, blocks_per_cu);
+    case 2: return occupancy_batched_d<2>(f16, block_threads, blocks_per_cu);
+    case 3: return occupancy_batched_d<3>(f16, block_threads, blocks_per_cu);
+    case 4: return occupancy_batched_d<4>(f16, block_threads, blocks_per_cu);
+    case 5: return occupancy_batched_d<5>(f16, block_threads, blocks_per_cu);
+    case 6: return occupancy_batched_d<6>(f16, block_threads, blocks_per_cu);
+    case 7: return occupancy_batched_d<7>(f16, block_threads, blocks_per_cu);
+    case 8: return occupancy_batched_d<8>(f16, block_threads, blocks_per_cu);
+    case 9: return occupancy_batched_d<9>(f16, block_threads, blocks_per_cu);
+    case 10: return occupancy_batched_d<10>(f16, block_threads, blocks_per_cu);
     default: return hipErrorInvalidValue;
     }
 }

@@ -39,6 +39,13 @@ class wrls_params(ctypes.Structure):
                 ("reserved", ctypes.c_int32 * 3)]
 
 
+class wrls_frame(ctypes.Structure):
+    _fields_ = [("color", ctypes.c_void_p), ("features", ctypes.c_void_p),
+                ("variance", ctypes.c_void_p), ("motion", ctypes.c_void_p), ("out", ctypes.c_void_p)]
+
+
+WRLS_MAX_BATCH = 64
+
 # Every symbol include/wrls.h declares, with its ctypes signature.
 _P = ctypes.POINTER(wrls_params)
 _VP = ctypes.c_void_p
@@ -49,6 +56,7 @@ SIGNATURES = {
     "wrls_state_bytes": (ctypes.c_size_t, [_P]),
     "wrls_stream_device_bytes": (ctypes.c_size_t, [_P]),
     "wrls_create_stream": (ctypes.c_int, [_P, _VP, ctypes.POINTER(_VP)]),
+    "wrls_create_stream_in": (ctypes.c_int, [_P, _VP, ctypes.c_size_t, _VP, ctypes.POINTER(_VP)]),
     "wrls_destroy": (ctypes.c_int, [_VP]),
     "wrls_set_hip_stream": (ctypes.c_int, [_VP, _VP]),
     "wrls_set_tile": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
@@ -59,6 +67,14 @@ SIGNATURES = {
     "wrls_step": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP]),
     "wrls_get_state": (ctypes.c_int, [_VP, _VP, _VP]),
     "wrls_set_state": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int64]),
+    "wrls_batch_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _VP,
+                                         ctypes.POINTER(_VP)]),
+    "wrls_batch_destroy": (ctypes.c_int, [_VP]),
+    "wrls_batch_hip_stream": (_VP, [_VP]),
+    "wrls_batch_set_tile": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "wrls_batch_use_graph": (ctypes.c_int, [_VP, ctypes.c_int32]),
+    "wrls_batch_step": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.POINTER(_VP),
+                                       ctypes.POINTER(wrls_frame)]),
     "wrls_last_error": (ctypes.c_char_p, []),
     "wrls_version": (ctypes.c_char_p, []),
 }
@@ -131,6 +147,14 @@ def wrls_create_stream(p: wrls_params, hip_stream: Optional[int] = None) -> int:
     return h.value
 
 
+def wrls_create_stream_in(p: wrls_params, device_mem: int, nbytes: int,
+                          hip_stream: Optional[int] = None) -> int:
+    h = ctypes.c_void_p()
+    _check(lib().wrls_create_stream_in(ctypes.byref(p), device_mem, nbytes, hip_stream,
+                                       ctypes.byref(h)))
+    return h.value
+
+
 def wrls_destroy(h: int):
     _check(lib().wrls_destroy(h))
 
@@ -170,6 +194,38 @@ def wrls_set_state(h: int, P_packed, beta, frames: int):
     _check(lib().wrls_set_state(h, _ptr(P_packed), _ptr(beta), frames))
 
 
+def wrls_batch_create(max_streams: int, d: int, in_dtype: int,
+                      hip_stream: Optional[int] = None) -> int:
+    h = ctypes.c_void_p()
+    _check(lib().wrls_batch_create(max_streams, d, in_dtype, hip_stream, ctypes.byref(h)))
+    return h.value
+
+
+def wrls_batch_destroy(b: int):
+    _check(lib().wrls_batch_destroy(b))
+
+
+def wrls_batch_hip_stream(b: int) -> Optional[int]:
+    return lib().wrls_batch_hip_stream(b)
+
+
+def wrls_batch_set_tile(b: int, tile_w_log2: int, block_threads: int, blocks_per_cu: int):
+    _check(lib().wrls_batch_set_tile(b, tile_w_log2, block_threads, blocks_per_cu))
+
+
+def wrls_batch_use_graph(b: int, enable: bool):
+    _check(lib().wrls_batch_use_graph(b, int(bool(enable))))
+
+
+def wrls_batch_step(b: int, handles, frames):
+    """handles: stream handles; frames: tuples (color, features, variance,
+    motion, out) of tensors (or None)."""
+    n = len(handles)
+    hs = (ctypes.c_void_p * max(n, 1))(*handles)
+    fs = (wrls_frame * max(n, 1))(*[wrls_frame(*[_ptr(t) for t in f]) for f in frames])
+    _check(lib().wrls_batch_step(b, n, hs, fs))
+
+
 def wrls_last_error() -> str:
     return lib().wrls_last_error().decode(errors="replace")
 
@@ -185,6 +241,14 @@ _WMODES = {"invvar": WRLS_W_INVVAR, "one": WRLS_W_ONE}
 _INTERPS = {"bilinear": WRLS_INTERP_BILINEAR, "nearest": WRLS_INTERP_NEAREST}
 
 
+def make_params(width, height, d, lam=0.98, delta=1.0, var_floor=1e-6, in_dtype="f32",
+                weight_mode="invvar", interp="bilinear") -> wrls_params:
+    p = wrls_params_default(width, height, d)
+    p.lambda_, p.delta, p.var_floor = lam, delta, var_floor
+    p.in_dtype, p.weight_mode, p.interp = _DTYPES[in_dtype], _WMODES[weight_mode], _INTERPS[interp]
+    return p
+
+
 class Stream:
     """One image sequence whose per-pixel models live on the GPU.
 
@@ -195,17 +259,21 @@ class Stream:
 
     def __init__(self, width: int, height: int, d: int, lam: float = 0.98, delta: float = 1.0,
                  var_floor: float = 1e-6, in_dtype: str = "f32", weight_mode: str = "invvar",
-                 interp: str = "bilinear", hip_stream: Optional[int] = None):
+                 interp: str = "bilinear", hip_stream: Optional[int] = None,
+                 device_mem: Optional[Tuple[int, int]] = None):
+        """device_mem: (pointer, bytes) of caller-owned device memory for the
+        state (wrls_create_stream_in); None: the library allocates."""
         import torch
         self._torch = torch
-        p = wrls_params_default(width, height, d)
-        p.lambda_, p.delta, p.var_floor = lam, delta, var_floor
-        p.in_dtype, p.weight_mode, p.interp = _DTYPES[in_dtype], _WMODES[weight_mode], _INTERPS[interp]
+        p = make_params(width, height, d, lam, delta, var_floor, in_dtype, weight_mode, interp)
         self.params = p
         self.W, self.H, self.d = width, height, d
         self.in_dtype = torch.float16 if in_dtype == "f16" else torch.float32
         self.hip_stream = _current_hip_stream() if hip_stream is None else hip_stream
-        self.handle = wrls_create_stream(p, self.hip_stream)
+        if device_mem is None:
+            self.handle = wrls_create_stream(p, self.hip_stream)
+        else:
+            self.handle = wrls_create_stream_in(p, device_mem[0], device_mem[1], self.hip_stream)
 
     def __del__(self):
         try:
@@ -269,3 +337,57 @@ class Stream:
         self._chk(P_packed, (d * (d + 1) // 2, H, W), torch.float32, "P_packed")
         self._chk(beta, (3, d, H, W), torch.float32, "beta")
         wrls_set_state(self.handle, P_packed, beta, frames)
+
+
+class Batch:
+    """Advances several Streams by one frame each with one persistent
+    launch (optionally a replayed HIP graph) on the batch's HIP stream."""
+
+    def __init__(self, max_streams: int, d: int, in_dtype: str = "f32",
+                 hip_stream: Optional[int] = None, use_graph: bool = True):
+        import torch
+        self._torch = torch
+        self.d = d
+        self.in_dtype = in_dtype
+        hs = _current_hip_stream() if hip_stream is None else hip_stream
+        self.handle = wrls_batch_create(max_streams, d, _DTYPES[in_dtype], hs)
+        self.hip_stream = wrls_batch_hip_stream(self.handle)
+        wrls_batch_use_graph(self.handle, use_graph)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def close(self):
+        h = getattr(self, "handle", None)
+        if h:
+            self.handle = None
+            wrls_batch_destroy(h)
+
+    def set_tile(self, tile_w_log2: int, block_threads: int, blocks_per_cu: int):
+        wrls_batch_set_tile(self.handle, tile_w_log2, block_threads, blocks_per_cu)
+
+    def use_graph(self, enable: bool):
+        wrls_batch_use_graph(self.handle, enable)
+
+    def step(self, streams, frames, outs=None):
+        """streams: list of Stream; frames: list of (color, features,
+        variance, motion) tensors; outs: optional output tensors.  Returns
+        the output tensors."""
+        torch = self._torch
+        if outs is None:
+            outs = [torch.empty((3, s.H, s.W), dtype=torch.float32, device="cuda") for s in streams]
+        full = []
+        for s, f, o in zip(streams, frames, outs):
+            c, fe, v, m = f
+            s._chk(c, (3, s.H, s.W), s.in_dtype, "color")
+            if s.d > 1:
+                s._chk(fe, (s.d - 1, s.H, s.W), s.in_dtype, "features")
+            s._chk(v, (s.H, s.W), torch.float32, "variance")
+            s._chk(m, (2, s.H, s.W), torch.float32, "motion")
+            s._chk(o, (3, s.H, s.W), torch.float32, "out")
+            full.append((c, fe if s.d > 1 else None, v, m, o))
+        wrls_batch_step(self.handle, [s.handle for s in streams], full)
+        return outs

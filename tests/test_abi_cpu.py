@@ -122,3 +122,28 @@ def test_last_error_is_thread_local():
     t.start()
     t.join()
     assert "d = 99" in mine and seen == [""]
+
+
+def test_batch_and_stream_in_reject_bad_arguments_without_gpu():
+    L = wrls.lib()
+    h = ctypes.c_void_p()
+    assert L.wrls_batch_create(0, 8, 0, None, ctypes.byref(h)) == wrls.WRLS_EINVAL
+    assert L.wrls_batch_create(wrls.WRLS_MAX_BATCH + 1, 8, 0, None, ctypes.byref(h)) == wrls.WRLS_EINVAL
+    assert L.wrls_batch_create(4, 11, 0, None, ctypes.byref(h)) == wrls.WRLS_EUNSUPPORTED
+    assert L.wrls_batch_create(4, 8, 3, None, ctypes.byref(h)) == wrls.WRLS_EINVAL
+    assert L.wrls_batch_create(4, 8, 0, None, None) == wrls.WRLS_EINVAL
+    assert L.wrls_batch_destroy(None) == wrls.WRLS_OK
+    assert L.wrls_batch_step(None, 0, None, None) == wrls.WRLS_EINVAL
+    assert L.wrls_batch_set_tile(None, 7, 256, 5) == wrls.WRLS_EINVAL
+    assert L.wrls_batch_use_graph(None, 1) == wrls.WRLS_EINVAL
+    assert L.wrls_batch_hip_stream(None) is None
+    p = wrls.wrls_params_default(64, 48, 8)
+    need = wrls.wrls_stream_device_bytes(p)
+    assert L.wrls_create_stream_in(ctypes.byref(p), None, need, None, ctypes.byref(h)) == wrls.WRLS_EINVAL
+    # checked before any device access: misaligned or too small regions
+    assert L.wrls_create_stream_in(ctypes.byref(p), ctypes.c_void_p(0x1000 + 4), need, None,
+                                   ctypes.byref(h)) == wrls.WRLS_EINVAL
+    assert "aligned" in wrls.wrls_last_error()
+    assert L.wrls_create_stream_in(ctypes.byref(p), ctypes.c_void_p(0x1000), need - 1, None,
+                                   ctypes.byref(h)) == wrls.WRLS_EINVAL
+    assert "needs" in wrls.wrls_last_error()

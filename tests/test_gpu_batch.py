@@ -1,0 +1,145 @@
+"""Batched persistent steps on the GPU: every stream's result is bitwise the
+same alone (wrls_step) and in the mix (wrls_batch_step, graph replay or plain
+launch), whatever else is in the batch; and matches the FP64 oracle."""
+import numpy as np
+import pytest
+
+import synth
+from parity import G1_TOL, g1, log, predictor, term_scale, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    yield
+
+
+def _mix(scale, frames, n=None):
+    wls = synth.c4_streams(frames=frames, scale=scale)
+    return wls[:n] if n else wls
+
+
+def _frames(wl, n):
+    src = synth.FrameSource(wl)
+    return [src.next() for _ in range(n)]
+
+
+def _dev(f):
+    return (to_dev(f.color), to_dev(f.feats), to_dev(f.var), to_dev(f.motion))
+
+
+def test_batch_equals_alone_bitwise_and_matches_oracle():
+    import oracle
+    import torch
+    from paper_2106_08034_amd import wrls
+    T = 6
+    wls = _mix(0.1, T, n=6)
+    host = [_frames(wl, T) for wl in wls]
+    dev = [[_dev(f) for f in fr] for fr in host]
+    alone = [wrls.Stream(wl.width, wl.height, wl.d, in_dtype="f16") for wl in wls]
+    b_graph = wrls.Batch(len(wls), 8, "f16")
+    cs = b_graph.hip_stream
+    mixed = [wrls.Stream(wl.width, wl.height, wl.d, in_dtype="f16", hip_stream=cs) for wl in wls]
+    b_plain = wrls.Batch(len(wls), 8, "f16", hip_stream=cs, use_graph=False)
+    plain = [wrls.Stream(wl.width, wl.height, wl.d, in_dtype="f16", hip_stream=cs) for wl in wls]
+    refs = [oracle.Oracle(wl.width, wl.height, wl.d) for wl in wls]
+    for t in range(T):
+        log("case batch mix frame %d" % t)
+        outs_a = [s.step(*dev[i][t]).clone() for i, s in enumerate(alone)]
+        outs_g = b_graph.step(mixed, [dev[i][t] for i in range(len(wls))])
+        outs_p = b_plain.step(plain, [dev[i][t] for i in range(len(wls))])
+        torch.cuda.synchronize()
+        for i, wl in enumerate(wls):
+            assert torch.equal(outs_a[i], outs_g[i]), (t, wl.name, "graph")
+            assert torch.equal(outs_a[i], outs_p[i]), (t, wl.name, "plain")
+            f = host[i][t]
+            ref = refs[i].step(f.color, f.feats, f.var, f.motion)
+            e = g1(outs_g[i].cpu().numpy(), ref, term_scale(refs[i].get_beta(), predictor(f.feats)))
+            assert e <= G1_TOL, (t, wl.name, e)
+
+
+def test_batch_changing_composition_and_empty_steps():
+    """Streams join and leave between steps (continuous batching); a stream's
+    frames give the same bits whatever shares its launch."""
+    import torch
+    from paper_2106_08034_amd import wrls
+    T = 7
+    wls = _mix(0.08, T, n=5)
+    dev = [[_dev(f) for f in _frames(wl, T)] for wl in wls]
+    alone = [wrls.Stream(wl.width, wl.height, 8, in_dtype="f16") for wl in wls]
+    ref = [[s.step(*dev[i][t]).clone() for t in range(T)] for i, s in enumerate(alone)]
+    b = wrls.Batch(5, 8, "f16")
+    mixed = [wrls.Stream(wl.width, wl.height, 8, in_dtype="f16", hip_stream=b.hip_stream) for wl in wls]
+    done = [0] * len(wls)
+    schedule = [[0, 1], [0, 1, 2], [], [2, 3, 4], [0, 4], [1, 2, 3, 4, 0], [1], [3], [0, 1, 2, 3, 4],
+                [2, 3, 4], [0, 1], [4, 0], [1, 2, 3], [2, 3, 4, 1, 0]]
+    for members in schedule:
+        members = [i for i in members if done[i] < T]
+        outs = b.step([mixed[i] for i in members], [dev[i][done[i]] for i in members])
+        torch.cuda.synchronize()
+        for i, o in zip(members, outs):
+            assert torch.equal(o, ref[i][done[i]]), (i, done[i])
+            done[i] += 1
+    assert min(done) >= 4
+
+
+def test_batch_rejects_duplicates_and_mismatches():
+    from paper_2106_08034_amd import wrls
+    b = wrls.Batch(2, 8, "f16")
+    s = wrls.Stream(32, 16, 8, in_dtype="f16", hip_stream=b.hip_stream)
+    t32 = wrls.Stream(32, 16, 8, in_dtype="f32", hip_stream=b.hip_stream)
+    s10 = wrls.Stream(32, 16, 10, in_dtype="f16", hip_stream=b.hip_stream)
+    fr = _dev(_frames(synth.c3(width=32, height=16, frames=1, d=8), 1)[0])
+    with pytest.raises(wrls.WrlsError, match="twice"):
+        b.step([s, s], [fr, fr])
+    with pytest.raises(wrls.WrlsError):
+        b.step([t32], [tuple(x.float() for x in fr)])
+    with pytest.raises(wrls.WrlsError):
+        wrls.wrls_batch_step(b.handle, [s10.handle], [(None, None, None, None, None)])
+    with pytest.raises(wrls.WrlsError):
+        wrls.wrls_batch_step(b.handle, [s.handle] * 3, [(None,) * 5] * 3)
+    assert s.frames == 0
+
+
+def test_stream_in_caller_memory_equals_library_allocation():
+    import torch
+    from paper_2106_08034_amd import wrls
+    wl = synth.c2(width=150, height=70, frames=5)
+    dev = [_dev(f) for f in _frames(wl, 5)]
+    p = wrls.make_params(wl.width, wl.height, wl.d)
+    need = wrls.wrls_stream_device_bytes(p)
+    arena = torch.empty(need // 4 + 64 + 1024, dtype=torch.float32, device="cuda")
+    ptr = (arena.data_ptr() + 255) // 256 * 256 + 4096
+    a = wrls.Stream(wl.width, wl.height, wl.d)
+    b = wrls.Stream(wl.width, wl.height, wl.d, device_mem=(ptr, need))
+    for f in dev:
+        assert torch.equal(a.step(*f).clone(), b.step(*f).clone())
+    b.close()
+    torch.cuda.synchronize()
+
+
+def test_full_size_c4_mix_batch_equals_alone():
+    """The 16-stream mix at its real resolutions (640x480 .. 2560x1440,
+    FP16, d = 8) for a few frames: the batched graph replay gives every
+    stream the bits of its own launch."""
+    import torch
+    from paper_2106_08034_amd import wrls
+    T = 3
+    wls = _mix(1.0, T)
+    log("case c4 full mix: " + ", ".join("%dx%d" % (w.width, w.height) for w in wls))
+    b = wrls.Batch(len(wls), 8, "f16")
+    alone = [wrls.Stream(wl.width, wl.height, 8, in_dtype="f16", hip_stream=b.hip_stream) for wl in wls]
+    mixed = [wrls.Stream(wl.width, wl.height, 8, in_dtype="f16", hip_stream=b.hip_stream) for wl in wls]
+    srcs = [synth.FrameSource(wl) for wl in wls]
+    for t in range(T):
+        fr = [_dev(s.next()) for s in srcs]
+        with torch.cuda.stream(torch.cuda.ExternalStream(b.hip_stream)):
+            outs_a = [s.step(*fr[i]) for i, s in enumerate(alone)]
+            outs_b = b.step(mixed, fr)
+        torch.cuda.synchronize()
+        for i in range(len(wls)):
+            assert torch.equal(outs_a[i], outs_b[i]), (t, wls[i].name)
