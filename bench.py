@@ -120,6 +120,35 @@ def bench_batched(args):
             torch.cuda.synchronize()
             wall = time.perf_counter() - t_start
         res[name] = {"ms_per_round": e0.elapsed_time(e1) / K, "wall_ms_per_round": wall * 1e3 / K}
+    # where launches dominate: 64 small streams (320x240, same recipe)
+    small = [synth.Workload(name="small-%02d" % i, width=320, height=240, frames=args.pool, d=8,
+                            in_dtype="f16", motion="pan", pan=(2.3, 0.0), disocclusion=0.05,
+                            config_index=3) for i in range(64)]
+    spools = []
+    for i, wl in enumerate(small):
+        src = synth.FrameSource(wl, stream=i)
+        spools.append([tuple(torch.from_numpy(a).cuda() for a in (f.color, f.feats, f.var, f.motion))
+                       for f in (src.next() for _ in range(2))])
+    sb = wrls.Batch(len(small), 8, "f16")
+    sm = [wrls.Stream(wl.width, wl.height, 8, in_dtype="f16", hip_stream=sb.hip_stream) for wl in small]
+    ss = [wrls.Stream(wl.width, wl.height, 8, in_dtype="f16", hip_stream=sb.hip_stream) for wl in small]
+    souts = [torch.empty((3, wl.height, wl.width), device="cuda") for wl in small]
+    sext = torch.cuda.ExternalStream(sb.hip_stream)
+    small_res = {}
+    for name, fn in (("batched_graph", lambda i: sb.step(sm, [p[i % 2] for p in spools], souts)),
+                     ("per_stream_launches",
+                      lambda i: [s.step(*p[i % 2], out=o) for s, p, o in zip(ss, spools, souts)])):
+        with torch.cuda.stream(sext):
+            for i in range(W):
+                fn(i)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(sext)
+            for i in range(K):
+                fn(W + i)
+            e1.record(sext)
+            torch.cuda.synchronize()
+        small_res[name] = e0.elapsed_time(e1) / K
     bpp = algorithmic_bytes_per_pixel(8, 2)
     b_ms = res["batched_graph"]["ms_per_round"]
     s_ms = res["per_stream_launches"]["ms_per_round"]
@@ -144,6 +173,8 @@ def bench_batched(args):
                                 "value": round(npix / (s_ms / 1e3) / 1e6, 2),
                                 "batched_speedup": round(s_ms / b_ms, 4)},
         "wall_ms_per_round": {k: round(v["wall_ms_per_round"], 4) for k, v in res.items()},
+        "small_frames_64x320x240": {k: round(v, 4) for k, v in small_res.items()} | {
+            "batched_speedup": round(small_res["per_stream_launches"] / small_res["batched_graph"], 3)},
         "cpu_baseline": None,
     }
 

@@ -174,15 +174,17 @@ wrls_status wrls_get_state(const wrls_stream *s, float *P_packed, float *beta);
 wrls_status wrls_set_state(wrls_stream *s, const float *P_packed, const float *beta,
                            int64_t frames);
 
-/* ---- Batched steps: many streams, one persistent launch ----------------
+/* ---- Batched steps: many streams, one launch ------------------------------
  *
- * A batch advances several streams by one frame each with ONE launch of a
- * persistent kernel whose grid is fixed (compute units x workgroups per CU):
- * the workgroups walk the concatenated tiles of all the frames.  The frames'
- * pointers go through a device-resident table that is refilled every step,
- * so the step can be captured once as a HIP graph and replayed for any
- * composition of streams (up to max_streams).  Each stream's result is
- * bitwise the same as with wrls_step. */
+ * A batch advances several streams by one frame each with ONE kernel launch
+ * over the concatenated tiles of all their frames.  The frames' pointers go
+ * through a device-resident table that is refilled every step, so the step
+ * is a HIP graph (table copy -> kernel) built once and replayed for any
+ * composition of streams (up to max_streams); only the kernel node's grid
+ * is updated when the tile count changes.  The grid gives each tile its own
+ * workgroup by default, or is a fixed persistent grid whose workgroups loop
+ * over the tiles.  Each stream's result is bitwise the same as with
+ * wrls_step. */
 
 /* Device pointers of one stream's frame; layouts as in wrls_step. */
 typedef struct {
@@ -213,14 +215,15 @@ wrls_status wrls_batch_destroy(wrls_batch *b);
 /* The batch's HIP stream (a hipStream_t). */
 void *wrls_batch_hip_stream(const wrls_batch *b);
 
-/* Launch shape: tile as in wrls_set_tile, and workgroups per compute unit
- * of the persistent grid (1..16; 0: as many as are resident at once, the
- * default).  Replaces any captured graph. */
+/* Launch shape: tile as in wrls_set_tile, and the grid: blocks_per_cu = 0
+ * (default) launches one workgroup per tile; 1..16 a persistent grid of that
+ * many workgroups per compute unit; -1 a persistent grid of as many as are
+ * resident at once.  Replaces the batch's graphs. */
 wrls_status wrls_batch_set_tile(wrls_batch *b, int32_t tile_w_log2, int32_t block_threads,
                                 int32_t blocks_per_cu);
 
-/* 1: replay a captured HIP graph per step (captured on first use);
- * 0: plain enqueue (copy of the table + launch).  Default 1. */
+/* 1: replay a HIP graph per step (built on first use); 0: plain enqueue
+ * (copy of the table + launch).  Default 1. */
 wrls_status wrls_batch_use_graph(wrls_batch *b, int32_t enable);
 
 /* One frame for each of streams[0..n-1] (distinct handles, same d and

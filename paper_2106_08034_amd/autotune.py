@@ -116,11 +116,13 @@ def tune_stream(width: int, height: int, d: int, frames: Sequence[tuple], in_dty
 
 def tune_batch(shapes: Sequence[Tuple[int, int]], d: int, frames: Sequence[Sequence[tuple]],
                in_dtype: str = "f16", candidates: Sequence[Tuple[int, int]] = TILE_CANDIDATES,
-               blocks_per_cu: Sequence[int] = (0,), steps: int = 6, warmup: int = 2,
+               blocks_per_cu: Sequence[int] = (0, -1), steps: int = 6, warmup: int = 2,
                cache: Optional[TuneCache] = None, force: bool = False):
     """Best (tile_w_log2, block_threads, blocks_per_cu) for batched steps of
-    streams with the given (width, height) shapes; frames[i]: device tensors
-    of stream i, cycled.  Returns (shape, timings)."""
+    streams with the given (width, height) shapes (blocks_per_cu 0: one
+    workgroup per tile, -1: resident persistent grid; see
+    wrls_batch_set_tile); frames[i]: device tensors of stream i, cycled.
+    Returns (shape, timings)."""
     cache = cache if cache is not None else TuneCache()
     total = sum(w * h for w, h in shapes)
     key = TuneCache.key(_device_name(), "batch%d" % len(shapes), d, in_dtype, total // max(1, len(shapes)))

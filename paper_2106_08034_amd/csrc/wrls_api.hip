@@ -347,27 +347,37 @@ struct wrls_batch {
     bool pending[2];
     int slot;
     wrls::TileShape tile;
-    int32_t blocks_per_cu;
+    int32_t blocks_per_cu;          // 0: one workgroup per tile; > 0: persistent grid
     int32_t cu_count;
     bool use_graph;
+    // per slot: graph of (table copy -> kernel); the kernel node's grid is
+    // updated when the tile count changes
+    hipGraph_t graph[2];            // kept alive: its node handles address the exec's nodes
     hipGraphExec_t exec[2];
+    hipGraphNode_t knode[2];
+    int32_t exec_grid[2];
+    const wrls::BatchTable *knode_arg[2];  // storage the kernel node's argument points to
 };
 
 namespace {
 
 void drop_graphs(wrls_batch *b)
 {
-    for (int i = 0; i < 2; i++)
+    for (int i = 0; i < 2; i++) {
         if (b->exec[i]) {
             (void)hipGraphExecDestroy(b->exec[i]);
             b->exec[i] = nullptr;
         }
+        if (b->graph[i]) {
+            (void)hipGraphDestroy(b->graph[i]);
+            b->graph[i] = nullptr;
+        }
+    }
 }
 
-// Workgroups per CU of the persistent grid by default: as many as are
-// resident at once (a larger grid would leave a tail of workgroups running
-// after the others, a smaller one idle slots).
-hipError_t default_blocks_per_cu(const wrls_batch *b, int32_t block_threads, int32_t *out)
+// Persistent grids default to as many workgroups per CU as are resident at
+// once (more would leave a tail running after the others).
+hipError_t resident_blocks_per_cu(const wrls_batch *b, int32_t block_threads, int32_t *out)
 {
     int n = 0;
     hipError_t e = wrls::batched_blocks_per_cu(b->d, b->in_dtype == WRLS_F16, block_threads, &n);
@@ -375,15 +385,59 @@ hipError_t default_blocks_per_cu(const wrls_batch *b, int32_t block_threads, int
     return e;
 }
 
-int32_t batch_grid(const wrls_batch *b) { return b->cu_count * b->blocks_per_cu; }
+// Workgroups of the launch over `tiles` tiles: a multiple of 8 (one part per
+// XCD), one tile each, or the fixed persistent grid.
+int32_t batch_grid(const wrls_batch *b, int32_t tiles)
+{
+    if (b->blocks_per_cu > 0) return b->cu_count * b->blocks_per_cu;
+    const int32_t g = (tiles + 7) / 8 * 8;
+    return g < 8 ? 8 : g;
+}
 
-// Enqueues the table copy and the persistent launch of slot i on b->st.
-hipError_t enqueue_step(wrls_batch *b, int i)
+hipKernelNodeParams kernel_params(wrls_batch *b, int i, int32_t grid)
+{
+    hipKernelNodeParams kp{};
+    kp.func = const_cast<void *>(wrls::batched_kernel_fn(b->d, b->in_dtype == WRLS_F16));
+    kp.gridDim = dim3((unsigned)grid);
+    kp.blockDim = dim3((unsigned)b->tile.block_threads);
+    kp.sharedMemBytes = 0;
+    b->knode_arg[i] = b->dev_tab[i];
+    static thread_local void *args[1];
+    args[0] = &b->knode_arg[i];
+    kp.kernelParams = args;
+    kp.extra = nullptr;
+    return kp;
+}
+
+// Builds slot i's graph: copy of the pinned table to the device table, then
+// the batched kernel over `grid` workgroups.
+hipError_t build_graph(wrls_batch *b, int i, int32_t grid)
+{
+    hipGraphNode_t mnode = nullptr;
+    hipError_t e = hipGraphCreate(&b->graph[i], 0);
+    if (e == hipSuccess)
+        e = hipGraphAddMemcpyNode1D(&mnode, b->graph[i], nullptr, 0, b->dev_tab[i], b->host_tab[i],
+                                    sizeof(wrls::BatchTable), hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        hipKernelNodeParams kp = kernel_params(b, i, grid);
+        e = hipGraphAddKernelNode(&b->knode[i], b->graph[i], &mnode, 1, &kp);
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->exec[i], b->graph[i], nullptr, nullptr, 0);
+    if (e == hipSuccess) {
+        b->exec_grid[i] = grid;
+    } else {
+        drop_graphs(b);
+    }
+    return e;
+}
+
+// Enqueues the table copy and the launch of slot i on b->st (no graph).
+hipError_t enqueue_step(wrls_batch *b, int i, int32_t grid)
 {
     hipError_t e = hipMemcpyAsync(b->dev_tab[i], b->host_tab[i], sizeof(wrls::BatchTable),
                                   hipMemcpyHostToDevice, b->st);
     if (e != hipSuccess) return e;
-    return wrls::launch_step_batched(b->d, b->in_dtype == WRLS_F16, b->dev_tab[i], batch_grid(b),
+    return wrls::launch_step_batched(b->d, b->in_dtype == WRLS_F16, b->dev_tab[i], grid,
                                      b->tile.block_threads, b->st);
 }
 
@@ -406,7 +460,8 @@ wrls_status wrls_batch_create(int32_t max_streams, int32_t d, int32_t in_dtype, 
     b->in_dtype = in_dtype;
     b->tile = default_tile();
     b->use_graph = true;
-    hipError_t e = default_blocks_per_cu(b, b->tile.block_threads, &b->blocks_per_cu);
+    b->blocks_per_cu = 0;
+    hipError_t e = hipSuccess;
     int dev = 0;
     if (e == hipSuccess) e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&b->cu_count, hipDeviceAttributeMultiprocessorCount, dev);
@@ -458,11 +513,11 @@ wrls_status wrls_batch_set_tile(wrls_batch *b, int32_t tile_w_log2, int32_t bloc
         return fail(WRLS_EINVAL, "block_threads = %d not in {64, 128, 256}", block_threads);
     if (tile_w_log2 < 0 || (1 << tile_w_log2) > block_threads)
         return fail(WRLS_EINVAL, "tile width 2^%d exceeds %d threads", tile_w_log2, block_threads);
-    if (blocks_per_cu < 0 || blocks_per_cu > 16)
-        return fail(WRLS_EINVAL, "blocks_per_cu = %d outside [0, 16]", blocks_per_cu);
+    if (blocks_per_cu < -1 || blocks_per_cu > 16)
+        return fail(WRLS_EINVAL, "blocks_per_cu = %d outside [-1, 16]", blocks_per_cu);
     hipError_t e = hipSuccess;
-    if (blocks_per_cu == 0) {
-        e = default_blocks_per_cu(b, block_threads, &blocks_per_cu);
+    if (blocks_per_cu == -1) {
+        e = resident_blocks_per_cu(b, block_threads, &blocks_per_cu);
         if (e != hipSuccess) return hip_fail(e, "occupancy query");
     }
     e = hipStreamSynchronize(b->st);
@@ -525,23 +580,21 @@ wrls_status wrls_batch_step(wrls_batch *b, int32_t n, wrls_stream *const *stream
         t->prefix[k + 1] = t->prefix[k] + a.tiles_x * a.tiles_y;
     }
     t->total_tiles = t->prefix[n];
+    const int32_t grid = batch_grid(b, t->total_tiles);
     hipError_t e = hipSuccess;
     if (b->use_graph) {
         if (!b->exec[i]) {
-            hipGraph_t g = nullptr;
-            e = hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal);
-            if (e == hipSuccess) {
-                hipError_t e2 = enqueue_step(b, i);
-                e = hipStreamEndCapture(b->st, &g);
-                if (e == hipSuccess) e = e2;
-            }
-            if (e == hipSuccess) e = hipGraphInstantiate(&b->exec[i], g, nullptr, nullptr, 0);
-            if (g) (void)hipGraphDestroy(g);
-            if (e != hipSuccess) return hip_fail(e, "batch graph capture");
+            e = build_graph(b, i, grid);
+            if (e != hipSuccess) return hip_fail(e, "batch graph construction");
+        } else if (b->exec_grid[i] != grid) {
+            hipKernelNodeParams kp = kernel_params(b, i, grid);
+            e = hipGraphExecKernelNodeSetParams(b->exec[i], b->knode[i], &kp);
+            if (e != hipSuccess) return hip_fail(e, "batch graph update");
+            b->exec_grid[i] = grid;
         }
         e = hipGraphLaunch(b->exec[i], b->st);
     } else {
-        e = enqueue_step(b, i);
+        e = enqueue_step(b, i, grid);
     }
     if (e != hipSuccess) return hip_fail(e, "batch step");
     e = hipEventRecord(b->done[i], b->st);

@@ -70,8 +70,10 @@ hipError_t launch_step(int d, bool f16, const FrameArgs &a, TileShape ts, hipStr
 // threads over every tile of every frame in the device table `tab`.
 hipError_t launch_step_batched(int d, bool f16, const BatchTable *tab, int32_t grid,
                                int32_t block_threads, hipStream_t st);
+// The batched kernel's entry point (for graph kernel nodes); null for a bad d.
+const void *batched_kernel_fn(int d, bool f16);
 // Workgroups of block_threads threads of the batched kernel that fit on one
-// compute unit at once (the persistent grid is this times the CU count).
+// compute unit at once.
 hipError_t batched_blocks_per_cu(int d, bool f16, int32_t block_threads, int *blocks_per_cu);
 
 }  // namespace wrls

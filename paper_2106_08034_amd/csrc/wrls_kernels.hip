@@ -320,6 +320,7 @@ hipError_t launch_step_d(bool f16, const FrameArgs &a, TileShape ts, hipStream_t
     const int tiles_x = (a.W + tw - 1) / tw;
     const int tiles_y = (a.H + th - 1) / th;
     FrameArgs b = a;
+    (void)hipGetLastError();  // report this launch's error, not an older one
     b.tiles_x = tiles_x;
     b.tiles_y = tiles_y;
     const int strip_w = ts.strip_w <= 0 ? tiles_x : ts.strip_w;
@@ -332,12 +333,16 @@ hipError_t launch_step_d(bool f16, const FrameArgs &a, TileShape ts, hipStream_t
     return hipGetLastError();
 }
 
-// Batched persistent step: a fixed grid walks the concatenated tiles of all
-// frames of the table.  Workgroup b (after the XCD remap) owns the contiguous
-// tile range [b T / G, (b + 1) T / G), so each XCD sweeps one run of
-// neighbouring tiles; tiles have equal cost, so equal ranges balance.  The
-// grid does not depend on the frames, so one captured graph serves every
-// batch composition; workgroups with an empty range exit at once.
+// Batched step: one launch over the concatenated tiles of all frames of the
+// table.  XCD k (the workgroups with blockIdx % 8 == k) owns the k-th eighth
+// of the tile list, and its workgroups stride through it in lock step, so at
+// any moment an XCD works on a compact window of consecutive tiles and
+// vertically adjacent tiles, which share source rows, meet in one L2.  With
+// a grid of 8 * ceil(tiles / 8) every workgroup takes one tile (the default:
+// a finished workgroup frees its slot while its stores drain); with a
+// smaller, fixed grid the kernel is persistent and its workgroups loop (on
+// gfx9 a looping wave's first wait for its next loads also waits for its
+// previous stores, which made that form ~20% slower on the 16-stream mix).
 // The loop bookkeeping costs the batched kernel ~10 registers over the
 // per-frame kernel; the occupancy hint keeps d <= 8 at 5 waves per SIMD
 // (94 registers, no spills), as the per-frame kernel; d = 10 spills at 5.
@@ -346,16 +351,22 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(D <= 8
 batch_kernel(const BatchTable *__restrict__ tab)
 {
     const int G = (int)gridDim.x;
-    const int b = xcd_tile((int)blockIdx.x, G);
+    const int xcd = (int)blockIdx.x % kNumXcd;
+    const int r = (int)blockIdx.x / kNumXcd;              // rank inside the XCD
+    const int on_xcd = G / kNumXcd + (xcd < G % kNumXcd);  // workgroups on this XCD
     const int total = tab->total_tiles;
-    const int t0 = (int)((int64_t)total * b / G);
-    const int t1 = (int)((int64_t)total * (b + 1) / G);
+    const int t0 = (int)((int64_t)total * xcd / kNumXcd);
+    const int t1 = (int)((int64_t)total * (xcd + 1) / kNumXcd);
     const int tw_log2 = tab->tile.tw_log2;
     const int th = tab->tile.block_threads >> tw_log2;
     const int lx = (int)threadIdx.x & ((1 << tw_log2) - 1);
     const int ly = (int)threadIdx.x >> tw_log2;
+    // frame of the first tile: count the frames that end at or before it
+    // (independent scalar loads, no dependent search)
     int f = 0;
-    for (int t = t0; t < t1; t++) {
+    const int n = tab->n;
+    for (int k = 1; k <= kMaxBatch; k++) f += (k <= n && tab->prefix[k] <= t0 + r) ? 1 : 0;
+    for (int t = t0 + r; t < t1; t += on_xcd) {
         while (t >= tab->prefix[f + 1]) f++;
         const FrameArgs a = tab->frame[f];
         const int local = t - tab->prefix[f];
@@ -381,6 +392,7 @@ template <int D>
 hipError_t launch_batched_d(bool f16, const BatchTable *tab, int32_t grid, int32_t block_threads,
                             hipStream_t st)
 {
+    (void)hipGetLastError();  // report this launch's error, not an older one
     if (f16)
         hipLaunchKernelGGL((batch_kernel<D, _Float16>), dim3((unsigned)grid),
                            dim3((unsigned)block_threads), 0, st, tab);
@@ -395,6 +407,7 @@ hipError_t launch_batched_d(bool f16, const BatchTable *tab, int32_t grid, int32
 hipError_t launch_reset(float *state, int64_t pitch, int64_t npix, int d, float p0,
                         hipStream_t st)
 {
+    (void)hipGetLastError();  // report this launch's error, not an older one
     const int64_t total = (int64_t)state_floats(d) * npix;
     int64_t blocks = (total + 255) / 256;
     if (blocks > 65536) blocks = 65536;
@@ -437,6 +450,28 @@ hipError_t launch_step_batched(int d, bool f16, const BatchTable *tab, int32_t g
     case 10: return launch_batched_d<10>(f16, tab, grid, block_threads, st);
     default: return hipErrorInvalidValue;
     }
+}
+
+const void *batched_kernel_fn(int d, bool f16)
+{
+#define WRLS_BATCH_FN(D)                                                                   \
+    case D:                                                                               \
+        return f16 ? reinterpret_cast<const void *>(&batch_kernel<D, _Float16>)            \
+                   : reinterpret_cast<const void *>(&batch_kernel<D, float>)
+    switch (d) {
+        WRLS_BATCH_FN(1);
+        WRLS_BATCH_FN(2);
+        WRLS_BATCH_FN(3);
+        WRLS_BATCH_FN(4);
+        WRLS_BATCH_FN(5);
+        WRLS_BATCH_FN(6);
+        WRLS_BATCH_FN(7);
+        WRLS_BATCH_FN(8);
+        WRLS_BATCH_FN(9);
+        WRLS_BATCH_FN(10);
+    default: return nullptr;
+    }
+#undef WRLS_BATCH_FN
 }
 
 hipError_t batched_blocks_per_cu(int d, bool f16, int32_t block_threads, int *blocks_per_cu)
