@@ -61,6 +61,34 @@ def make_workload(name: str):
     raise SystemExit("unknown workload %r" % name)
 
 
+def bench_serving(args):
+    """32 sessions (Poisson 4/s arrivals, Exp(20 s) durations, 720p..4K,
+    30..60 Hz, FP16, d = 8) served in real time for args.serve_seconds:
+    HBM-budget admission, continuous batching, two steps in flight.
+    Returns the server's report (Mpix/s, p50/p99 latency, ...)."""
+    import torch
+
+    import synth
+    from paper_2106_08034_amd.serve import Server
+
+    sessions = synth.c5_sessions()
+    t0 = time.time()
+    pools = {}
+    for i, (w, h) in enumerate(synth.C5_RESOLUTIONS):
+        src = synth.FrameSource(synth.c5_frame_pool(w, h, args.pool), stream=i)
+        pools[(w, h)] = [tuple(torch.from_numpy(a).cuda() for a in (f.color, f.feats, f.var, f.motion))
+                         for f in (src.next() for _ in range(args.pool))]
+    torch.cuda.synchronize()
+    print("serving: generated %d frames per resolution in %.1fs" % (args.pool, time.time() - t0),
+          file=sys.stderr, flush=True)
+    budget = int((args.budget_gb or 200.0) * (1 << 30))
+    srv = Server(budget_bytes=budget, max_batch=32)
+    res, _ = srv.run(sessions, pools, seconds=args.serve_seconds)
+    res["budget_gb"] = round(budget / (1 << 30), 2)
+    res["frames_cycled_per_resolution"] = args.pool
+    return res
+
+
 def bench_batched(args):
     """16 streams of mixed resolution (640x480 .. 2560x1440), FP16 inputs,
     d = 8: one persistent batched launch per round (HIP graph replay) against
@@ -184,7 +212,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=60)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--serve-seconds", type=float, default=15.0,
+                    help="c5 (and the default run's serving leg): wall seconds of serving")
+    ap.add_argument("--budget-gb", type=float, default=0.0,
+                    help="c5: HBM budget for session state (0: 200 GB)")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="default run: skip the short serving leg")
     ap.add_argument("--pool", type=int, default=4,
                     help="c4: distinct frames generated per stream (cycled)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -226,6 +260,20 @@ def main():
 
     if args.workload == "c4":
         print(json.dumps(bench_batched(args)), flush=True)
+        return
+    if args.workload == "c5":
+        res = bench_serving(args)
+        line = {"metric": "denoised Mpix/s + p50/p99 frame latency @32 sessions (serving)",
+                "value": res["mpix_per_s"], "unit": "Mpix/s", "n_gpus": 1,
+                "steps": res["steps"], "warmup": 0,
+                "ms_per_step": round(res["seconds"] * 1e3 / max(1, res["steps"]), 4),
+                "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                "dtype": "f32 (f16 inputs)",
+                "data": "synthetic (seeded sessions and procedural frames)",
+                "config": {"workload": "c5-32-sessions-poisson4-exp20s-720p..4k-30..60Hz-d8-f16",
+                           "serve_seconds": args.serve_seconds}, "serving": res,
+                "cpu_baseline": None}
+        print(json.dumps(line), flush=True)
         return
     wl = make_workload(args.workload)
     t0 = time.time()
@@ -311,6 +359,13 @@ def main():
         "cpu_baseline": cpu,
     }
     stream.close()
+    if not args.no_serving and args.workload == "c2":
+        del dev_frames
+        torch.cuda.empty_cache()
+        sv = bench_serving(args)
+        line["serving_32_sessions"] = {k: sv[k] for k in ("mpix_per_s", "p50_ms", "p99_ms", "max_ms",
+                                                          "frames", "steps", "max_concurrent",
+                                                          "sessions_served", "seconds")}
     print(json.dumps(line), flush=True)
 
 

@@ -399,3 +399,39 @@ def frames(wl: Workload, stream: int = 0, count: Optional[int] = None):
     src = FrameSource(wl, stream)
     n = wl.frames if count is None else count
     return [src.next() for _ in range(n)]
+
+
+@dataclasses.dataclass(frozen=True)
+class Session:
+    """One viewer of the serving workload."""
+    sid: int
+    width: int
+    height: int
+    fps: float
+    arrival: float    # seconds after the start
+    duration: float   # seconds
+
+
+def c5_sessions(n: int = 32, rate: float = 4.0, mean_duration: float = 20.0,
+                resolutions=C5_RESOLUTIONS, fps_range=(30.0, 60.0)):
+    """The serving workload: n sessions with Poisson(rate) arrivals,
+    Exp(mean_duration) durations, a resolution drawn uniformly from
+    `resolutions` and a frame rate uniform in fps_range."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(SEED_BASE + 4)))
+    gaps = rng.exponential(1.0 / rate, size=n)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    out = []
+    for i in range(n):
+        w, h = resolutions[int(rng.integers(len(resolutions)))]
+        out.append(Session(sid=i, width=w, height=h, fps=float(rng.uniform(*fps_range)),
+                           arrival=float(arrivals[i]),
+                           duration=float(rng.exponential(mean_duration))))
+    return out
+
+
+def c5_frame_pool(width: int, height: int, count: int, stream: int = 0) -> Workload:
+    """Pre-generated frames of one serving resolution (pan, FP16, d = 8),
+    cycled by the sessions of that resolution."""
+    return Workload(name="c5-pool-%dx%d" % (width, height), width=width, height=height,
+                    frames=count, d=8, in_dtype="f16", motion="pan", pan=(2.3, 0.0),
+                    disocclusion=0.05, config_index=4)

@@ -1,0 +1,84 @@
+"""Serving logic without a GPU: arena allocation, admission by footprint,
+batch composition, retirement."""
+import pytest
+
+import synth
+from paper_2106_08034_amd.serve import ALIGN, Arena, Scheduler, SessionState, percentile
+
+
+def test_arena_first_fit_alignment_and_coalescing():
+    a = Arena(10 * ALIGN)
+    x = a.alloc(1)
+    y = a.alloc(ALIGN + 1)
+    z = a.alloc(3 * ALIGN)
+    assert (x, y, z) == (0, ALIGN, 3 * ALIGN)
+    assert all(o % ALIGN == 0 for o in (x, y, z))
+    assert a.alloc(5 * ALIGN) is None          # only 4 * ALIGN left at the end
+    a.release(y)
+    assert a.alloc(3 * ALIGN) == 6 * ALIGN      # first fit skips the 2-ALIGN hole
+    a.release(x)
+    assert a.free[0] == (0, 3 * ALIGN)          # x and y's holes merged
+    a.release(z)
+    a.release(6 * ALIGN)
+    assert a.free == [(0, 10 * ALIGN)] and a.bytes_used == 0
+
+
+def _sess(sid, w=100, h=50, fps=50.0, arrival=0.0, dur=1.0):
+    return SessionState(sid, w, h, fps, arrival, arrival + dur)
+
+
+def test_admission_by_footprint_in_arrival_order():
+    fp = lambda w, h: w * h * 100
+    sch = Scheduler(budget=1_200_000, footprint=fp, max_batch=8)
+    big = _sess(0, 100, 100)      # 1.0 MB
+    small = _sess(1, 10, 10)      # 10 kB
+    huge = _sess(2, 200, 100)     # 2 MB: can never fit
+    for s in (big, small, huge):
+        sch.arrive(s)
+    assert sch.rejected == [huge]
+    assert [s.sid for s in sch.admit(0.0)] == [0, 1]
+    late = _sess(3, 100, 50)      # 0.5 MB: waits for memory
+    sch.arrive(late)
+    assert sch.admit(0.1) == [] and sch.waiting == [late]
+    big.next_frame = 1000          # past its end
+    assert [s.sid for s in sch.retire(10.0)] == [0]
+    assert [s.sid for s in sch.admit(10.0)] == [3]
+    assert late.admitted_at == 10.0
+
+
+def test_batch_composition_one_frame_in_flight_and_due_frames():
+    sch = Scheduler(budget=10 ** 9, footprint=lambda w, h: 1000, max_batch=2)
+    a, b, c = _sess(0, fps=10), _sess(1, fps=100), _sess(2, fps=100)
+    for s in (a, b, c):
+        sch.arrive(s)
+    sch.admit(0.0)
+    assert len(sch.active) == 3
+    assert [s.sid for s in sch.next_batch(0.0)] == [0, 1]      # max_batch caps the step
+    a.in_flight = True
+    assert [s.sid for s in sch.next_batch(0.0)] == [1, 2]
+    a.in_flight = False
+    a.next_frame = 1               # next frame of a due at 0.1 s
+    b.next_frame = 3               # due at 0.03 s
+    c.next_frame = 2               # due at 0.02 s: the oldest goes first
+    assert [s.sid for s in sch.next_batch(0.05)] == [2, 1]
+    c.next_frame = 9               # due at 0.09 s
+    assert [s.sid for s in sch.next_batch(0.1)] == [1, 2]
+    b.in_flight = True
+    assert [s.sid for s in sch.next_batch(0.1)] == [2, 0]
+
+
+def test_sessions_workload_is_seeded_and_shaped():
+    s1, s2 = synth.c5_sessions(), synth.c5_sessions()
+    assert s1 == s2 and len(s1) == 32
+    assert all((x.width, x.height) in synth.C5_RESOLUTIONS for x in s1)
+    assert all(30.0 <= x.fps <= 60.0 for x in s1)
+    arr = [x.arrival for x in s1]
+    assert arr == sorted(arr) and arr[0] == 0.0
+    # Poisson(4/s): 31 gaps with mean about 1/4 s
+    assert 0.1 < (arr[-1] / 31) < 0.5
+
+
+def test_percentile():
+    assert percentile([3, 1, 2], 50) == 2
+    assert percentile([1, 2, 3, 4], 100) == 4
+    assert percentile(list(range(101)), 99) == pytest.approx(99)
