@@ -318,18 +318,25 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
+        # the oracle as it stands, on the same frames: whole passes over the
+        # first n_cpu frames of the sequence until about 10 s of CPU work
         import oracle
         n_cpu = args.cpu_frames or wl.frames
-        o = oracle.Oracle(wl.width, wl.height, wl.d, lam=0.98)
+        passes = 0
+        frames_done = 0
         tc = time.perf_counter()
-        for f in host_frames[:n_cpu]:
-            o.step(f.color, f.feats, f.var, f.motion)
+        while passes < 8 and (passes == 0 or time.perf_counter() - tc < 10.0):
+            o = oracle.Oracle(wl.width, wl.height, wl.d, lam=0.98)
+            for f in host_frames[:n_cpu]:
+                o.step(f.color, f.feats, f.var, f.motion)
+            del o
+            passes += 1
+            frames_done += n_cpu
         cpu_s = time.perf_counter() - tc
-        cpu = {"value": round(n_cpu * npix / cpu_s / 1e6, 3), "unit": "Mpix/s",
+        cpu = {"value": round(frames_done * npix / cpu_s / 1e6, 3), "unit": "Mpix/s",
                "cores": oracle.threads(), "kind": "oracle",
-               "sample": "FP64 C oracle (OpenMP over rows) on the first %d frames of the same "
-                         "%s sequence, %.1f s" % (n_cpu, wl.name, cpu_s)}
-        del o
+               "sample": "FP64 C oracle (OpenMP over rows), %d pass(es) over the first %d frames "
+                         "of the same %s sequence, %.1f s" % (passes, n_cpu, wl.name, cpu_s)}
 
     line = {
         "metric": "denoised Mpix/s (wRLS step) + % HBM roofline",
