@@ -21,6 +21,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 W_INVVAR = 0
 W_ONE = 1
+W_PAPER = 2
 INTERP_BILINEAR = 0
 INTERP_NEAREST = 1
 
@@ -61,6 +62,10 @@ def _load():
     lib.oracle_frames.restype = ctypes.c_long
     lib.oracle_frames.argtypes = [ctypes.c_void_p]
     lib.oracle_set_origin.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]
+    lib.oracle_set_paper_params.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
+                                            ctypes.c_double]
+    lib.oracle_get_history.argtypes = [ctypes.c_void_p, dp]
+    lib.oracle_set_history.argtypes = [ctypes.c_void_p, dp]
     lib.oracle_threads.restype = ctypes.c_int
     lib.oracle_threads.argtypes = []
     lib.oracle_step.restype = ctypes.c_int
@@ -98,10 +103,14 @@ class Oracle:
 
     lam: forgetting factor; delta: prior precision (P starts at I/delta,
     beta at 0); var_floor: smallest variance turned into a weight.
+    wmode W_PAPER (d = 4): the predictor is the temporal feature of Eq. 12
+    (alpha) and the weight that of Eq. 13 (h_bw, eps); features and variance
+    are then not used.
     """
 
     def __init__(self, width, height, d, lam=0.98, delta=1.0, var_floor=1e-6,
-                 wmode=W_INVVAR, interp=INTERP_BILINEAR, origin=(0, 0)):
+                 wmode=W_INVVAR, interp=INTERP_BILINEAR, origin=(0, 0), alpha=0.75, h_bw=0.75,
+                 eps=1e-4):
         self._lib = _load()
         self.W, self.H, self.d = int(width), int(height), int(d)
         self.lam, self.delta = float(lam), float(delta)
@@ -113,6 +122,8 @@ class Oracle:
         # a crop of a larger image: source positions are rounded in that
         # image's coordinates (see oracle_set_origin)
         self._lib.oracle_set_origin(h, int(origin[0]), int(origin[1]))
+        # paper mode (Eq. 12-13): history weight alpha, bandwidth h, epsilon
+        self._lib.oracle_set_paper_params(h, float(alpha), float(h_bw), float(eps))
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -135,7 +146,7 @@ class Oracle:
         want_prior."""
         W, H, d = self.W, self.H, self.d
         c = _f64(color, (3, H, W))
-        f = _f64(feats, (d - 1, H, W)) if d > 1 else None
+        f = _f64(feats, (d - 1, H, W)) if (d > 1 and feats is not None) else None
         v = _f64(var, (H, W)) if var is not None else None
         m = _f64(motion, (2, H, W)) if motion is not None else None
         out = np.zeros((3, H, W), np.float64)
@@ -160,6 +171,16 @@ class Oracle:
         beta = np.zeros((3, self.d, self.H, self.W), np.float64)
         self._lib.oracle_get_beta(self._h, _ptr(beta))
         return beta
+
+    def get_history(self):
+        """Paper mode: the temporal feature history z, (3,H,W)."""
+        z = np.zeros((3, self.H, self.W), np.float64)
+        self._lib.oracle_get_history(self._h, _ptr(z))
+        return z
+
+    def set_history(self, z):
+        z = _f64(z, (3, self.H, self.W))
+        self._lib.oracle_set_history(self._h, _ptr(z))
 
     def set_state(self, P, beta, frames=1):
         W, H, d = self.W, self.H, self.d

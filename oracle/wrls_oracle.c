@@ -33,6 +33,15 @@
  * Colour channels share P and w and keep one beta row each (Sec. 5.1 treats
  * channels independently with the same predictor).
  *
+ * Paper mode (Sec. 5.3): the predictor is the temporal feature instead of
+ * supplied features, p = [1, z] (d = 4), with
+ *   z(t) = alpha Psi[z_q(t-1), I~(t)] + (1 - alpha) I~(t)     (Eq. 12)
+ * where z_q(t-1) is the history reprojected like the model and Psi clamps it,
+ * per channel, to the range of I~(t) over the 3x3 neighbourhood of the pixel;
+ * with no history z(t) = I~(t).  The weight is
+ *   w = exp(-dist^2 / h^2),  dist = |I~ - z| / (min(|I~|, |z|) + eps)  (Eq. 13)
+ * with Euclidean norms over the three channels.
+ *
  * Parity pins: closed-form exponentially weighted least squares, the d = 1
  * weighted mean, brute-force stacked design matrices (Eq. 7), SPD and
  * symmetry of P, the noise-free identities, exact integer shifts and exact
@@ -46,6 +55,7 @@
 
 #define ORACLE_W_INVVAR 0
 #define ORACLE_W_ONE 1
+#define ORACLE_W_PAPER 2
 
 #define ORACLE_INTERP_BILINEAR 0
 #define ORACLE_INTERP_NEAREST 1
@@ -58,10 +68,12 @@ typedef struct oracle {
     int wmode;
     int interp;
     int ox, oy;        /* position of pixel (0, 0) in a larger image (crops) */
+    double alpha, h, eps;  /* paper mode: Eq. 12 history weight, Eq. 13 bandwidth and epsilon */
     long frames;       /* frames processed since creation or reset */
     /* Per-pixel state, pixel-major: P is d*d (full, row-major), beta 3*d. */
     double *P_cur, *beta_cur;
     double *P_prev, *beta_prev;
+    double *z_cur, *z_prev;  /* paper mode: temporal feature history, 3 per pixel */
 } oracle;
 
 static size_t npix(const oracle *o) { return (size_t)o->W * (size_t)o->H; }
@@ -80,20 +92,25 @@ oracle *oracle_create(int W, int H, int d, double lambda, double delta,
 {
     if (W <= 0 || H <= 0 || d < 1 || d > 32) return NULL;
     if (!(lambda > 0.0 && lambda <= 1.0) || !(delta > 0.0)) return NULL;
-    if (wmode != ORACLE_W_INVVAR && wmode != ORACLE_W_ONE) return NULL;
+    if (wmode != ORACLE_W_INVVAR && wmode != ORACLE_W_ONE && wmode != ORACLE_W_PAPER) return NULL;
+    if (wmode == ORACLE_W_PAPER && d != 4) return NULL;
     if (interp != ORACLE_INTERP_BILINEAR && interp != ORACLE_INTERP_NEAREST) return NULL;
     oracle *o = (oracle *)calloc(1, sizeof(oracle));
     if (!o) return NULL;
     o->W = W; o->H = H; o->d = d;
     o->lambda = lambda; o->delta = delta; o->var_floor = var_floor;
     o->wmode = wmode; o->interp = interp;
+    o->alpha = 0.75; o->h = 0.75; o->eps = 1e-4;
     size_t n = npix(o);
     o->P_cur = (double *)malloc(n * d * d * sizeof(double));
     o->P_prev = (double *)malloc(n * d * d * sizeof(double));
     o->beta_cur = (double *)malloc(n * 3 * d * sizeof(double));
     o->beta_prev = (double *)malloc(n * 3 * d * sizeof(double));
-    if (!o->P_cur || !o->P_prev || !o->beta_cur || !o->beta_prev) {
+    o->z_cur = (double *)calloc(n * 3, sizeof(double));
+    o->z_prev = (double *)calloc(n * 3, sizeof(double));
+    if (!o->P_cur || !o->P_prev || !o->beta_cur || !o->beta_prev || !o->z_cur || !o->z_prev) {
         free(o->P_cur); free(o->P_prev); free(o->beta_cur); free(o->beta_prev);
+        free(o->z_cur); free(o->z_prev);
         free(o);
         return NULL;
     }
@@ -107,6 +124,7 @@ void oracle_destroy(oracle *o)
 {
     if (!o) return;
     free(o->P_cur); free(o->P_prev); free(o->beta_cur); free(o->beta_prev);
+    free(o->z_cur); free(o->z_prev);
     free(o);
 }
 
@@ -127,6 +145,12 @@ long oracle_frames(const oracle *o) { return o->frames; }
  * so a crop reproduces the full image's arithmetic bit for bit (pixels whose
  * sources fall outside the crop restart, as at an image border). */
 void oracle_set_origin(oracle *o, int ox, int oy) { o->ox = ox; o->oy = oy; }
+
+/* Paper-mode parameters: alpha of Eq. 12, h and eps of Eq. 13. */
+void oracle_set_paper_params(oracle *o, double alpha, double h, double eps)
+{
+    o->alpha = alpha; o->h = h; o->eps = eps;
+}
 
 /* Threads the per-row loop of oracle_step runs on. */
 int oracle_threads(void) { return omp_get_max_threads(); }
@@ -181,6 +205,75 @@ static int reproject(const oracle *o, int x, int y, double vx_in, double vy_in,
         beta[i] = w00 * o->beta_prev[s00 * 3 * d + i] + w10 * o->beta_prev[s10 * 3 * d + i]
                 + w01 * o->beta_prev[s01 * 3 * d + i] + w11 * o->beta_prev[s11 * 3 * d + i];
     return 1;
+}
+
+/* The history z of the previous frame at the same source position, with the
+ * same taps and weights as reproject() uses for the model. */
+static void reproject_history(const oracle *o, int x, int y, double vx_in, double vy_in,
+                              double *zq)
+{
+    int W = o->W, H = o->H;
+    float sx = ((float)(x + o->ox) + (float)vx_in) - (float)o->ox;
+    float sy = ((float)(y + o->oy) + (float)vy_in) - (float)o->oy;
+    if (o->interp == ORACLE_INTERP_NEAREST) {
+        int xn = (int)floorf(sx + 0.5f), yn = (int)floorf(sy + 0.5f);
+        if (xn > W - 1) xn = W - 1;
+        if (yn > H - 1) yn = H - 1;
+        for (int c = 0; c < 3; c++) zq[c] = o->z_prev[((size_t)yn * W + xn) * 3 + c];
+        return;
+    }
+    float fx0 = floorf(sx), fy0 = floorf(sy);
+    int x0 = (int)fx0, y0 = (int)fy0;
+    double fx = (double)(sx - fx0), fy = (double)(sy - fy0);
+    int x1 = x0 + 1 < W ? x0 + 1 : W - 1;
+    int y1 = y0 + 1 < H ? y0 + 1 : H - 1;
+    for (int c = 0; c < 3; c++)
+        zq[c] = (1.0 - fx) * (1.0 - fy) * o->z_prev[((size_t)y0 * W + x0) * 3 + c]
+              + fx * (1.0 - fy) * o->z_prev[((size_t)y0 * W + x1) * 3 + c]
+              + (1.0 - fx) * fy * o->z_prev[((size_t)y1 * W + x0) * 3 + c]
+              + fx * fy * o->z_prev[((size_t)y1 * W + x1) * 3 + c];
+}
+
+/* Temporal feature (Eq. 12).  color: the frame's planar colour; yc: this
+ * pixel's colour (finite); zq: reprojected history, used when have_hist. */
+static void temporal_feature(const oracle *o, const double *color, int x, int y, int have_hist,
+                             const double *zq, const double *yc, double *z)
+{
+    int W = o->W, H = o->H;
+    size_t n = npix(o);
+    for (int c = 0; c < 3; c++) {
+        if (!have_hist) {
+            z[c] = yc[c];
+            continue;
+        }
+        /* Psi: clamp to the range of the current colour over the 3x3
+         * neighbourhood (inside the image, finite values only) */
+        double lo = INFINITY, hi = -INFINITY;
+        for (int dy = -1; dy <= 1; dy++)
+            for (int dx = -1; dx <= 1; dx++) {
+                int nx = x + dx, ny = y + dy;
+                if (nx < 0 || ny < 0 || nx >= W || ny >= H) continue;
+                double v = color[(size_t)c * n + (size_t)ny * W + nx];
+                if (!isfinite(v)) continue;
+                if (v < lo) lo = v;
+                if (v > hi) hi = v;
+            }
+        double psi = zq[c] < lo ? lo : (zq[c] > hi ? hi : zq[c]);
+        z[c] = o->alpha * psi + (1.0 - o->alpha) * yc[c];
+    }
+}
+
+/* Weight of Eq. 13 from the colour and the temporal feature. */
+static double feature_weight(const oracle *o, const double *yc, const double *z)
+{
+    double dd = 0.0, ny = 0.0, nz = 0.0;
+    for (int c = 0; c < 3; c++) {
+        dd += (yc[c] - z[c]) * (yc[c] - z[c]);
+        ny += yc[c] * yc[c];
+        nz += z[c] * z[c];
+    }
+    double dist = sqrt(dd) / (fmin(sqrt(ny), sqrt(nz)) + o->eps);
+    return exp(-(dist * dist) / (o->h * o->h));
 }
 
 /* Weight of the current sample: inverse variance, or 1 for plain RLS.
@@ -276,7 +369,9 @@ int oracle_step(oracle *o, const double *color, const double *feats, const doubl
     double *t;
     t = o->P_prev; o->P_prev = o->P_cur; o->P_cur = t;
     t = o->beta_prev; o->beta_prev = o->beta_cur; o->beta_cur = t;
+    t = o->z_prev; o->z_prev = o->z_cur; o->z_cur = t;
     long frame = o->frames;
+    int paper = o->wmode == ORACLE_W_PAPER;
 
 #pragma omp parallel for schedule(dynamic, 1)
     for (int y = y0; y < y1; y++) {
@@ -286,22 +381,38 @@ int oracle_step(oracle *o, const double *color, const double *feats, const doubl
             double *beta = o->beta_cur + j * 3 * d;
             double p[32], yc[3], o3[3], pr3[3];
 
-            p[0] = 1.0;
-            for (int i = 1; i < d; i++) p[i] = feats[(size_t)(i - 1) * n + j];
             for (int c = 0; c < 3; c++) yc[c] = color[(size_t)c * n + j];
-            double v = var ? var[j] : 1.0;
-            double w = sample_weight(o, yc, p, v);
-            if (w == 0.0)  /* keep non-finite predictor entries out of P */
-                for (int i = 0; i < d; i++)
-                    if (!isfinite(p[i])) p[i] = 0.0;
-
             int have = 0;
-            if (frame > 0) {
-                double vx = motion ? motion[j] : 0.0;
-                double vy = motion ? motion[n + j] : 0.0;
-                have = reproject(o, x, y, vx, vy, P, beta);
-            }
+            double vx = motion ? motion[j] : 0.0;
+            double vy = motion ? motion[n + j] : 0.0;
+            if (frame > 0) have = reproject(o, x, y, vx, vy, P, beta);
             if (!have) init_pixel(o, P, beta);
+
+            double w;
+            p[0] = 1.0;
+            if (paper) {
+                double zq[3] = {0.0, 0.0, 0.0}, z[3];
+                if (have) reproject_history(o, x, y, vx, vy, zq);
+                if (isfinite(yc[0]) && isfinite(yc[1]) && isfinite(yc[2])) {
+                    temporal_feature(o, color, x, y, have, zq, yc, z);
+                    w = feature_weight(o, yc, z);
+                } else {
+                    /* no usable sample: the history is carried unchanged */
+                    for (int c = 0; c < 3; c++) z[c] = zq[c];
+                    w = 0.0;
+                }
+                for (int c = 0; c < 3; c++) {
+                    p[1 + c] = z[c];
+                    o->z_cur[j * 3 + c] = z[c];
+                }
+            } else {
+                for (int i = 1; i < d; i++) p[i] = feats[(size_t)(i - 1) * n + j];
+                double v = var ? var[j] : 1.0;
+                w = sample_weight(o, yc, p, v);
+                if (w == 0.0)  /* keep non-finite predictor entries out of P */
+                    for (int i = 0; i < d; i++)
+                        if (!isfinite(p[i])) p[i] = 0.0;
+            }
 
             update_pixel(o, P, beta, p, yc, w, pr3, o3);
             for (int c = 0; c < 3; c++) {
@@ -323,6 +434,21 @@ void oracle_get_state(const oracle *o, double *P, double *beta)
         for (int i = 0; i < d * d; i++) P[(size_t)i * n + j] = o->P_cur[j * d * d + i];
         for (int i = 0; i < 3 * d; i++) beta[(size_t)i * n + j] = o->beta_cur[j * 3 * d + i];
     }
+}
+
+/* Paper mode: the temporal feature history, planar [3][H][W]. */
+void oracle_get_history(const oracle *o, double *z)
+{
+    size_t n = npix(o);
+    for (size_t j = 0; j < n; j++)
+        for (int c = 0; c < 3; c++) z[(size_t)c * n + j] = o->z_cur[j * 3 + c];
+}
+
+void oracle_set_history(oracle *o, const double *z)
+{
+    size_t n = npix(o);
+    for (size_t j = 0; j < n; j++)
+        for (int c = 0; c < 3; c++) o->z_cur[j * 3 + c] = z[(size_t)c * n + j];
 }
 
 /* beta alone, planar [3][d][H][W]. */

@@ -36,6 +36,21 @@ MUTANTS = {
     "output_a_priori": ("        out[c] = acc;\n", "        out[c] = prior_out ? prior_out[c] : acc;\n"),
     "features_reversed": ("p[i] = feats[(size_t)(i - 1) * n + j];", "p[i] = feats[(size_t)(d - 1 - i) * n + j];"),
     "outlier_not_skipped": ("    if (!isfinite(var) || var < 0.0) return 0.0;\n", ""),
+    # paper mode (Eq. 12-13)
+    "eq12_alpha_swapped": ("z[c] = o->alpha * psi + (1.0 - o->alpha) * yc[c];",
+                           "z[c] = (1.0 - o->alpha) * psi + o->alpha * yc[c];"),
+    "eq12_no_clamp": ("double psi = zq[c] < lo ? lo : (zq[c] > hi ? hi : zq[c]);",
+                      "double psi = zq[c];"),
+    "eq12_clamp_bounds_swapped": ("if (v < lo) lo = v;\n                if (v > hi) hi = v;",
+                                  "if (v > lo) lo = v;\n                if (v < hi) hi = v;"),
+    "eq12_no_history_is_zero": ("            z[c] = yc[c];\n            continue;",
+                                "            z[c] = 0.0;\n            continue;"),
+    "eq13_not_squared": ("return exp(-(dist * dist) / (o->h * o->h));", "return exp(-dist / (o->h * o->h));"),
+    "eq13_max_norm": ("fmin(sqrt(ny), sqrt(nz))", "fmax(sqrt(ny), sqrt(nz))"),
+    "history_reprojection_nearest": ("              + fx * (1.0 - fy) * o->z_prev[((size_t)y0 * W + x1) * 3 + c]",
+                                     "              + fx * (1.0 - fy) * o->z_prev[((size_t)y0 * W + x0) * 3 + c]"),
+    "history_not_carried": ("                    for (int c = 0; c < 3; c++) z[c] = zq[c];",
+                            "                    for (int c = 0; c < 3; c++) z[c] = 0.0;"),
 }
 
 
@@ -43,7 +58,8 @@ MUTANTS = {
 def test_pins_catch_planted_mistake(name, tmp_path):
     old, new = MUTANTS[name]
     src = open(SRC).read()
-    assert src.count(old) == 1, "mutation site not found: %s" % name
+    # a site repeated in the history reprojection is mutated everywhere
+    assert src.count(old) >= 1, "mutation site not found: %s" % name
     mutant = tmp_path / "mutant.c"
     mutant.write_text(src.replace(old, new))
     lib = tmp_path / "libmutant.so"
@@ -51,6 +67,7 @@ def test_pins_catch_planted_mistake(name, tmp_path):
                     "-w", "-o", str(lib), str(mutant), "-lm"], check=True)
     env = dict(os.environ, WRLS_ORACLE_LIB_OVERRIDE=str(lib), OMP_NUM_THREADS="2")
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_paper_pins.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=300)
     assert r.returncode != 0, "planted mistake %r passed every pin:\n%s" % (name, r.stdout[-2000:])
