@@ -61,7 +61,18 @@ typedef enum { WRLS_F32 = 0, WRLS_F16 = 1 } wrls_dtype;
 
 typedef enum {
     WRLS_W_INVVAR = 0,  /* w = 1 / max(variance, var_floor) */
-    WRLS_W_ONE = 1      /* w = 1: plain RLS, Eq. 10 (variance may be NULL) */
+    WRLS_W_ONE = 1,     /* w = 1: plain RLS, Eq. 10 (variance may be NULL) */
+    WRLS_W_PAPER = 2    /* the paper's own predictor and weight (Sec. 5.3), d = 4:
+                         * p = [1, z] with the temporal feature
+                         *   z(t) = alpha Psi[z_q(t-1), I~(t)] + (1 - alpha) I~(t)  (Eq. 12),
+                         * Psi clamping the reprojected history z_q per channel to
+                         * the range of I~(t) over the pixel's 3x3 neighbourhood (z = I~
+                         * without history), and w = exp(-dist^2 / h^2),
+                         * dist = |I~ - z| / (min(|I~|, |z|) + eps)  (Eq. 13).
+                         * features and variance are not used (may be NULL); the
+                         * history adds 3 state entries per pixel.  The colour
+                         * enters p, so p P p^T holds its square: colours above
+                         * about 1e18 overflow binary32 there (the gain becomes 0). */
 } wrls_weight_mode;
 
 typedef enum { WRLS_INTERP_BILINEAR = 0, WRLS_INTERP_NEAREST = 1 } wrls_interp;
@@ -78,14 +89,18 @@ typedef struct {
     int32_t in_dtype;       /* wrls_dtype of colour and features */
     int32_t weight_mode;    /* wrls_weight_mode */
     int32_t interp;         /* wrls_interp */
-    int32_t reserved[3];    /* must be zero */
+    float alpha;            /* WRLS_W_PAPER: history weight of Eq. 12, in [0, 1] */
+    float h;                /* WRLS_W_PAPER: bandwidth of Eq. 13, > 0, 1/h^2 finite */
+    float eps;              /* WRLS_W_PAPER: epsilon of Eq. 13, > 0 (finite) */
+    int32_t reserved[2];    /* must be zero */
 } wrls_params;
 
 typedef struct wrls_stream wrls_stream;  /* opaque, owned by the library */
 
 /* Fills *p with defaults for a width x height image and predictor length d:
  * lambda 0.98, delta 1, var_floor 1e-6, FP32 inputs, inverse-variance
- * weights, bilinear reprojection.  A null p is ignored. */
+ * weights, bilinear reprojection; alpha 0.75, h 0.75, eps 1e-4 (the values
+ * Sec. 5.3 and 6 use).  A null p is ignored. */
 void wrls_params_default(wrls_params *p, int32_t width, int32_t height, int32_t d);
 
 /* Checks a parameter block without touching the GPU: WRLS_OK or
@@ -95,9 +110,10 @@ void wrls_params_default(wrls_params *p, int32_t width, int32_t height, int32_t 
  * about 17.9 Mpixel at d = 8 and 12.6 Mpixel at d = 10 (3840x2160 is 8.3). */
 wrls_status wrls_params_validate(const wrls_params *p);
 
-/* Floats of state per pixel: d(d+1)/2 for the packed upper triangle of P
- * (Sec. 5.2: P is the d x d inverse covariance, symmetric) plus 3d for beta
- * (one coefficient row per colour channel, Sec. 5.1).  0 for a bad d. */
+/* Floats of model state per pixel: d(d+1)/2 for the packed upper triangle of
+ * P (Sec. 5.2: P is the d x d inverse covariance, symmetric) plus 3d for
+ * beta (one coefficient row per colour channel, Sec. 5.1).  0 for a bad d.
+ * WRLS_W_PAPER streams hold 3 more (the history z). */
 int32_t wrls_state_floats(int32_t d);
 
 /* Device bytes of ONE copy of the per-pixel state of a stream with these
@@ -174,6 +190,12 @@ wrls_status wrls_get_state(const wrls_stream *s, float *P_packed, float *beta);
 wrls_status wrls_set_state(wrls_stream *s, const float *P_packed, const float *beta,
                            int64_t frames);
 
+/* WRLS_W_PAPER streams: copies the temporal feature history z out / in
+ * ([3][H][W] floats, device pointers, stream-ordered).  WRLS_EINVAL for
+ * other streams. */
+wrls_status wrls_get_history(const wrls_stream *s, float *z);
+wrls_status wrls_set_history(wrls_stream *s, const float *z);
+
 /* ---- Batched steps: many streams, one launch ------------------------------
  *
  * A batch advances several streams by one frame each with ONE kernel launch
@@ -227,8 +249,8 @@ wrls_status wrls_batch_set_tile(wrls_batch *b, int32_t tile_w_log2, int32_t bloc
 wrls_status wrls_batch_use_graph(wrls_batch *b, int32_t enable);
 
 /* One frame for each of streams[0..n-1] (distinct handles, same d and
- * in_dtype as the batch, n <= max_streams); frames[i] belongs to
- * streams[i].  Stream-ordered on the batch's HIP stream; returns without
+ * in_dtype as the batch, n <= max_streams, not WRLS_W_PAPER); frames[i]
+ * belongs to streams[i].  Stream-ordered on the batch's HIP stream; returns without
  * synchronising. */
 wrls_status wrls_batch_step(wrls_batch *b, int32_t n, wrls_stream *const *streams,
                             const wrls_frame *frames);

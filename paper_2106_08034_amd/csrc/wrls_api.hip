@@ -50,6 +50,12 @@ int64_t plane_pitch(const wrls_params *p)
 
 wrls::TileShape default_tile() { return wrls::TileShape{7, 256, 0}; }
 
+// State entries per pixel of a stream: the model, plus the history in paper mode.
+int stream_state_floats(const wrls_params *p)
+{
+    return wrls::state_floats(p->d) + (p->weight_mode == WRLS_W_PAPER ? 3 : 0);
+}
+
 }  // namespace
 
 extern "C" {
@@ -67,6 +73,9 @@ void wrls_params_default(wrls_params *p, int32_t width, int32_t height, int32_t 
     p->in_dtype = WRLS_F32;
     p->weight_mode = WRLS_W_INVVAR;
     p->interp = WRLS_INTERP_BILINEAR;
+    p->alpha = 0.75f;
+    p->h = 0.75f;
+    p->eps = 1e-4f;
 }
 
 wrls_status wrls_params_validate(const wrls_params *p)
@@ -84,15 +93,28 @@ wrls_status wrls_params_validate(const wrls_params *p)
         return fail(WRLS_EINVAL, "var_floor = %g must be finite and >= 0", (double)p->var_floor);
     if (p->in_dtype != WRLS_F32 && p->in_dtype != WRLS_F16)
         return fail(WRLS_EINVAL, "in_dtype = %d unknown", p->in_dtype);
-    if (p->weight_mode != WRLS_W_INVVAR && p->weight_mode != WRLS_W_ONE)
+    if (p->weight_mode != WRLS_W_INVVAR && p->weight_mode != WRLS_W_ONE &&
+        p->weight_mode != WRLS_W_PAPER)
         return fail(WRLS_EINVAL, "weight_mode = %d unknown", p->weight_mode);
+    if (p->weight_mode == WRLS_W_PAPER) {
+        if (p->d != 4) return fail(WRLS_EINVAL, "WRLS_W_PAPER needs d = 4 (p = [1, z]), got %d", p->d);
+        if (!(p->alpha >= 0.0f && p->alpha <= 1.0f))
+            return fail(WRLS_EINVAL, "alpha = %g outside [0, 1]", (double)p->alpha);
+        // 1/h^2 must be finite in binary32, or a zero distance gives 0 * inf
+        if (!(p->h > 0.0f) || !std::isfinite(p->h) || !std::isfinite(1.0f / (p->h * p->h)))
+            return fail(WRLS_EINVAL, "h = %g: 1/h^2 must be finite and h > 0", (double)p->h);
+        // eps > 0 keeps the distance of a black pixel whose history is black
+        // defined (0 / 0 otherwise)
+        if (!(p->eps > 0.0f) || !std::isfinite(p->eps))
+            return fail(WRLS_EINVAL, "eps = %g must be finite and > 0", (double)p->eps);
+    }
     if (p->interp != WRLS_INTERP_BILINEAR && p->interp != WRLS_INTERP_NEAREST)
         return fail(WRLS_EINVAL, "interp = %d unknown", p->interp);
-    for (int i = 0; i < 3; i++)
+    for (int i = 0; i < 2; i++)
         if (p->reserved[i] != 0) return fail(WRLS_EINVAL, "reserved fields must be zero");
     // The kernels address every array with 32-bit byte offsets; the state
     // copy is the largest array of a stream.
-    const uint64_t copy = (uint64_t)wrls::state_floats(p->d) * sizeof(float) *
+    const uint64_t copy = (uint64_t)stream_state_floats(p) * sizeof(float) *
                           (uint64_t)plane_pitch(p);
     if (copy > 0xFFFFFFFFull)
         return fail(WRLS_EUNSUPPORTED,
@@ -110,13 +132,13 @@ int32_t wrls_state_floats(int32_t d)
 size_t wrls_state_bytes(const wrls_params *p)
 {
     if (wrls_params_validate(p) != WRLS_OK) return 0;
-    return (size_t)wrls::state_floats(p->d) * sizeof(float) * (size_t)p->width * (size_t)p->height;
+    return (size_t)stream_state_floats(p) * sizeof(float) * (size_t)p->width * (size_t)p->height;
 }
 
 size_t wrls_stream_device_bytes(const wrls_params *p)
 {
     if (wrls_params_validate(p) != WRLS_OK) return 0;
-    return 2 * (size_t)wrls::state_floats(p->d) * sizeof(float) * (size_t)plane_pitch(p);
+    return 2 * (size_t)stream_state_floats(p) * sizeof(float) * (size_t)plane_pitch(p);
 }
 
 namespace {
@@ -135,11 +157,12 @@ wrls_status init_stream(const wrls_params *p, void *hip_stream, void *mem, bool 
     s->tile = default_tile();
     s->alloc = mem;
     s->owns_alloc = owns;
-    const size_t one = (size_t)wrls::state_floats(p->d) * (size_t)s->pitch;
+    const size_t one = (size_t)stream_state_floats(p) * (size_t)s->pitch;
     s->state[0] = static_cast<float *>(mem);
     s->state[1] = s->state[0] + one;
     const int64_t npix = (int64_t)p->width * p->height;
-    hipError_t e = wrls::launch_reset(s->state[0], s->pitch, npix, p->d, 1.0f / p->delta, s->st);
+    hipError_t e = wrls::launch_reset(s->state[0], s->pitch, npix, p->d, stream_state_floats(p),
+                                      1.0f / p->delta, s->st);
     if (e != hipSuccess) {
         delete s;
         return hip_fail(e, "state initialisation");
@@ -227,7 +250,7 @@ wrls_status wrls_reset(wrls_stream *s)
     if (!s) return fail(WRLS_EINVAL, "stream handle is NULL");
     const int64_t npix = (int64_t)s->prm.width * s->prm.height;
     hipError_t e = wrls::launch_reset(s->state[s->cur], s->pitch, npix, s->prm.d,
-                                      1.0f / s->prm.delta, s->st);
+                                      stream_state_floats(&s->prm), 1.0f / s->prm.delta, s->st);
     if (e != hipSuccess) return hip_fail(e, "reset launch");
     s->frames = 0;
     return WRLS_OK;
@@ -246,13 +269,18 @@ wrls_status frame_args(const wrls_stream *s, const void *color, const void *feat
     const wrls_params &p = s->prm;
     if (!color) return fail(WRLS_EINVAL, "color is NULL");
     if (!out) return fail(WRLS_EINVAL, "out is NULL");
-    if (p.d > 1 && !features) return fail(WRLS_EINVAL, "features is NULL with d = %d", p.d);
+    const bool paper = p.weight_mode == WRLS_W_PAPER;
+    if (p.d > 1 && !paper && !features)
+        return fail(WRLS_EINVAL, "features is NULL with d = %d", p.d);
     if (p.weight_mode == WRLS_W_INVVAR && !variance)
         return fail(WRLS_EINVAL, "variance is NULL with inverse-variance weights");
     *a = wrls::FrameArgs{};
     a->color = color;
-    a->feats = features;
+    a->feats = paper ? nullptr : features;
     a->var = p.weight_mode == WRLS_W_INVVAR ? variance : nullptr;
+    a->alpha = p.alpha;
+    a->inv_h2 = 1.0f / (p.h * p.h);
+    a->eps = p.eps;
     a->motion = motion;
     a->out = out;
     a->state_in = s->state[s->cur];
@@ -285,7 +313,10 @@ wrls_status wrls_step(wrls_stream *s, const void *color, const void *features,
     wrls::FrameArgs a;
     wrls_status rc = frame_args(s, color, features, variance, motion, out, &a);
     if (rc != WRLS_OK) return rc;
-    hipError_t e = wrls::launch_step(s->prm.d, s->prm.in_dtype == WRLS_F16, a, s->tile, s->st);
+    const bool f16 = s->prm.in_dtype == WRLS_F16;
+    hipError_t e = s->prm.weight_mode == WRLS_W_PAPER
+                       ? wrls::launch_step_paper(f16, a, s->tile, s->st)
+                       : wrls::launch_step(s->prm.d, f16, a, s->tile, s->st);
     if (e != hipSuccess) return hip_fail(e, "step launch");
     advance(s);
     return WRLS_OK;
@@ -545,6 +576,8 @@ wrls_status wrls_batch_step(wrls_batch *b, int32_t n, wrls_stream *const *stream
     for (int i = 0; i < n; i++) {
         const wrls_stream *s = streams[i];
         if (!s) return fail(WRLS_EINVAL, "streams[%d] is NULL", i);
+        if (s->prm.weight_mode == WRLS_W_PAPER)
+            return fail(WRLS_EUNSUPPORTED, "streams[%d]: batches do not take WRLS_W_PAPER streams", i);
         if (s->prm.d != b->d || s->prm.in_dtype != b->in_dtype)
             return fail(WRLS_EINVAL, "streams[%d] has d = %d, dtype %d; the batch takes d = %d, dtype %d",
                         i, s->prm.d, s->prm.in_dtype, b->d, b->in_dtype);
@@ -602,6 +635,32 @@ wrls_status wrls_batch_step(wrls_batch *b, int32_t n, wrls_stream *const *stream
     b->pending[i] = true;
     b->slot = 1 - i;
     for (int k = 0; k < n; k++) advance(streams[k]);
+    return WRLS_OK;
+}
+
+wrls_status wrls_get_history(const wrls_stream *s, float *z)
+{
+    if (!s) return fail(WRLS_EINVAL, "stream handle is NULL");
+    if (s->prm.weight_mode != WRLS_W_PAPER) return fail(WRLS_EINVAL, "the stream has no history");
+    if (!z) return fail(WRLS_EINVAL, "z is NULL");
+    const size_t n = (size_t)s->prm.width * s->prm.height;
+    const float *src = s->state[s->cur] + (size_t)wrls::state_floats(s->prm.d) * s->pitch;
+    hipError_t e = hipMemcpy2DAsync(z, n * sizeof(float), src, (size_t)s->pitch * sizeof(float),
+                                    n * sizeof(float), 3, hipMemcpyDeviceToDevice, s->st);
+    if (e != hipSuccess) return hip_fail(e, "history export");
+    return WRLS_OK;
+}
+
+wrls_status wrls_set_history(wrls_stream *s, const float *z)
+{
+    if (!s) return fail(WRLS_EINVAL, "stream handle is NULL");
+    if (s->prm.weight_mode != WRLS_W_PAPER) return fail(WRLS_EINVAL, "the stream has no history");
+    if (!z) return fail(WRLS_EINVAL, "z is NULL");
+    const size_t n = (size_t)s->prm.width * s->prm.height;
+    float *dst = s->state[s->cur] + (size_t)wrls::state_floats(s->prm.d) * s->pitch;
+    hipError_t e = hipMemcpy2DAsync(dst, (size_t)s->pitch * sizeof(float), z, n * sizeof(float),
+                                    n * sizeof(float), 3, hipMemcpyDeviceToDevice, s->st);
+    if (e != hipSuccess) return hip_fail(e, "history import");
     return WRLS_OK;
 }
 

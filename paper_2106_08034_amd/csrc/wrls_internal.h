@@ -33,6 +33,7 @@ struct FrameArgs {
     int32_t W, H;
     int64_t pitch;          // floats between state planes
     float lambda, inv_lambda, p0, var_floor;
+    float alpha, inv_h2, eps;  // paper mode: Eq. 12 history weight, 1/h^2 and eps of Eq. 13
     int32_t fresh;          // 1: no history (first frame)
     int32_t unit_weight;    // 1: w = 1 (plain RLS)
     int32_t nearest;        // 1: nearest reprojection
@@ -63,9 +64,13 @@ struct BatchTable {
     FrameArgs frame[kMaxBatch];
 };
 
-hipError_t launch_reset(float *state, int64_t pitch, int64_t npix, int d, float p0,
+// S: state entries per pixel (state_floats(d), plus 3 history entries in
+// paper mode).
+hipError_t launch_reset(float *state, int64_t pitch, int64_t npix, int d, int S, float p0,
                         hipStream_t st);
 hipError_t launch_step(int d, bool f16, const FrameArgs &a, TileShape ts, hipStream_t st);
+// The paper's own predictor and weight (d = 4, state with history).
+hipError_t launch_step_paper(bool f16, const FrameArgs &a, TileShape ts, hipStream_t st);
 // One persistent launch of `grid` workgroups of tab->tile.block_threads
 // threads over every tile of every frame in the device table `tab`.
 hipError_t launch_step_batched(int d, bool f16, const BatchTable *tab, int32_t grid,

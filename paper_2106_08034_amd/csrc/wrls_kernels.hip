@@ -80,12 +80,162 @@ __device__ __forceinline__ float load_in(Rsrc r, const _Float16 *, uint32_t n, i
 
 __device__ __forceinline__ bool finite(float v) { return __builtin_isfinite(v); }
 
-// The per-pixel update.  D: predictor length; InT: colour/feature type.
+// Reprojection (Sec. 5.3, Table 2: pi(v_j) = j + v_j in the previous frame):
+// the NS state entries of pixel (x, y) gathered from the previous frame's
+// state at (x, y) + v.  Returns false when the pixel has no valid source
+// (first frame, non-finite motion, source outside the image).
+template <int NS>
+__device__ __forceinline__ bool gather_state(const FrameArgs &a, int x, int y, uint32_t j,
+                                             uint32_t n, float (&st)[NS])
+{
+    if (a.fresh) return false;
+    float vx = 0.0f, vy = 0.0f;
+    if (a.motion) {
+        const Rsrc r_mot = array_rsrc(a.motion, 2u * n * 4u);
+        vx = bload(r_mot, j * 4u, 0u);
+        vy = bload(r_mot, j * 4u, n * 4u);
+    }
+    const float sx = (float)x + vx;
+    const float sy = (float)y + vy;
+    // NaN fails every comparison and +-inf lands outside: both restart.
+    if (!(sx >= 0.0f && sx <= (float)(a.W - 1) && sy >= 0.0f && sy <= (float)(a.H - 1)))
+        return false;
+    const uint32_t pbytes = (uint32_t)a.pitch * 4u;
+    const Rsrc src = array_rsrc(a.state_in, (uint32_t)NS * pbytes);
+    if (a.nearest) {
+        const int xn = min((int)floorf(sx + 0.5f), a.W - 1);
+        const int yn = min((int)floorf(sy + 0.5f), a.H - 1);
+        const uint32_t o = ((uint32_t)yn * (uint32_t)a.W + (uint32_t)xn) * 4u;
+#pragma unroll
+        for (int k = 0; k < NS; k++) st[k] = bload(src, o, (uint32_t)k * pbytes);
+        return true;
+    }
+    const float fx0 = floorf(sx), fy0 = floorf(sy);
+    const float fx = sx - fx0, fy = sy - fy0;
+    const int x0 = (int)fx0, y0 = (int)fy0;
+    const int x1 = min(x0 + 1, a.W - 1), y1 = min(y0 + 1, a.H - 1);
+    const uint32_t W = (uint32_t)a.W;
+    const uint32_t o00 = ((uint32_t)y0 * W + (uint32_t)x0) * 4u;
+    const uint32_t o10 = ((uint32_t)y0 * W + (uint32_t)x1) * 4u;
+    const uint32_t o01 = ((uint32_t)y1 * W + (uint32_t)x0) * 4u;
+    const uint32_t o11 = ((uint32_t)y1 * W + (uint32_t)x1) * 4u;
+    // Bilinear in nested-lerp form (exact for a constant field).  Entries go
+    // in groups of kGatherGroup: the group's 4 * kGatherGroup loads are issued
+    // back to back, so many are in flight per wave, before any is consumed.
+#pragma unroll
+    for (int k0 = 0; k0 < NS; k0 += kGatherGroup) {
+        float t00[kGatherGroup], t10[kGatherGroup], t01[kGatherGroup], t11[kGatherGroup];
+#pragma unroll
+        for (int g = 0; g < kGatherGroup; g++) {
+            if (k0 + g < NS) {
+                const uint32_t so = (uint32_t)(k0 + g) * pbytes;
+                t00[g] = bload(src, o00, so);
+                t10[g] = bload(src, o10, so);
+                t01[g] = bload(src, o01, so);
+                t11[g] = bload(src, o11, so);
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int g = 0; g < kGatherGroup; g++) {
+            if (k0 + g < NS) {
+                const float top = fmaf(fx, t10[g] - t00[g], t00[g]);
+                const float bot = fmaf(fx, t11[g] - t01[g], t01[g]);
+                st[k0 + g] = fmaf(fy, bot - top, top);
+            }
+        }
+    }
+    return true;
+}
+
+// The model of a pixel without history: P = I / delta (packed), beta = 0.
+template <int D>
+__device__ __forceinline__ void init_model(float p0, float *P, float *B)
+{
+#pragma unroll
+    for (int i = 0; i < D; i++)
+#pragma unroll
+        for (int m = i; m < D; m++) P[packed_index(D, i, m)] = (i == m) ? p0 : 0.0f;
+#pragma unroll
+    for (int k = 0; k < 3 * D; k++) B[k] = 0.0f;
+}
+
+// One weighted RLS update in place (Sec. 5.2-5.3) of the packed P and of B
+// (3 rows of D) with predictor p, colour yc and weight w (ok: the sample is
+// usable); out receives the a-posteriori prediction.
+template <int D>
+__device__ __forceinline__ void rls_update(float *P, float *B, const float (&p)[D],
+                                           const float (&yc)[3], float w, bool ok, float lambda,
+                                           float inv_lambda, float (&out)[3])
+{
+    // Gain (Eq. 14, multiplied through by w): k = P p^T, s = p k,
+    // q = g k with g = w / (lambda + w s); g = 0 when w = 0.
+    float kv[D];
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int m = 0; m < D; m++)
+            acc = fmaf(P[i <= m ? packed_index(D, i, m) : packed_index(D, m, i)], p[m], acc);
+        kv[i] = acc;
+    }
+    float s = 0.0f;
+#pragma unroll
+    for (int i = 0; i < D; i++) s = fmaf(p[i], kv[i], s);
+    const float g = w / fmaf(w, s, lambda);
+
+    // Residual against the previous coefficients (Eq. 8) and update (Eq. 9),
+    // then the a-posteriori prediction (Eq. 6).
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        float pred = 0.0f;
+#pragma unroll
+        for (int i = 0; i < D; i++) pred = fmaf(p[i], B[c * D + i], pred);
+        const float ge = ok ? g * (yc[c] - pred) : 0.0f;
+        float post = 0.0f;
+#pragma unroll
+        for (int i = 0; i < D; i++) {
+            B[c * D + i] = fmaf(ge, kv[i], B[c * D + i]);
+            post = fmaf(p[i], B[c * D + i], post);
+        }
+        out[c] = post;
+    }
+
+    // Inverse covariance (Eq. 11): P <- (P - g k k^T) / lambda on the upper
+    // triangle; symmetric by construction.
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+        const float gki = g * kv[i];
+#pragma unroll
+        for (int m = i; m < D; m++) {
+            const int idx = packed_index(D, i, m);
+            P[idx] = fmaf(-gki, kv[m], P[idx]) * inv_lambda;
+        }
+    }
+}
+
+// Stores the NS state entries of pixel j and its output.
+template <int NS>
+__device__ __forceinline__ void store_pixel(const FrameArgs &a, uint32_t j, uint32_t n,
+                                            const float (&st)[NS], const float (&out)[3])
+{
+    const uint32_t pbytes = (uint32_t)a.pitch * 4u;
+    const Rsrc dst = array_rsrc(a.state_out, (uint32_t)NS * pbytes);
+    const Rsrc r_out = array_rsrc(a.out, 3u * n * 4u);
+    const uint32_t oj = j * 4u;
+#pragma unroll
+    for (int k = 0; k < NS; k++) bstore(dst, oj, (uint32_t)k * pbytes, st[k]);
+#pragma unroll
+    for (int c = 0; c < 3; c++) bstore(r_out, oj, (uint32_t)c * n * 4u, out[c]);
+}
+
+// The per-pixel update with supplied features.  D: predictor length; InT:
+// colour/feature type.  State: packed P (D(D+1)/2 entries), then beta.
 template <int D, typename InT>
 __device__ __forceinline__ void update_pixel(const FrameArgs &a, int x, int y)
 {
     constexpr int NP = packed_floats(D);
-    constexpr int NB = 3 * D;
+    constexpr int NS = state_floats(D);
     const uint32_t n = (uint32_t)a.W * (uint32_t)a.H;
     const uint32_t j = (uint32_t)y * (uint32_t)a.W + (uint32_t)x;
     const InT *tag = nullptr;  // selects the input type's loader
@@ -119,138 +269,90 @@ __device__ __forceinline__ void update_pixel(const FrameArgs &a, int x, int y)
         for (int i = 1; i < D; i++) p[i] = finite(p[i]) ? p[i] : 0.0f;
     }
 
-    // Reprojection: fetch the model at j + v from the previous frame.
-    float P[NP], B[NB];
-    bool have = false;
-    if (!a.fresh) {
-        float vx = 0.0f, vy = 0.0f;
-        if (a.motion) {
-            const Rsrc r_mot = array_rsrc(a.motion, 2u * n * 4u);
-            vx = bload(r_mot, j * 4u, 0u);
-            vy = bload(r_mot, j * 4u, n * 4u);
-        }
-        const float sx = (float)x + vx;
-        const float sy = (float)y + vy;
-        // NaN fails every comparison and +-inf lands outside: both restart.
-        have = sx >= 0.0f && sx <= (float)(a.W - 1) && sy >= 0.0f && sy <= (float)(a.H - 1);
+    float st[NS];
+    if (!gather_state<NS>(a, x, y, j, n, st)) init_model<D>(a.p0, st, st + NP);
+    float out[3];
+    rls_update<D>(st, st + NP, p, yc, w, ok, a.lambda, a.inv_lambda, out);
+    store_pixel<NS>(a, j, n, st, out);
+}
+
+// The per-pixel update with the paper's own predictor and weight (Sec. 5.3):
+// p = [1, z] with the temporal feature z of Eq. 12 and the weight of Eq. 13.
+// State: packed P (10), beta (12), then the history z (3).
+template <typename InT>
+__device__ __forceinline__ void update_pixel_paper(const FrameArgs &a, int x, int y)
+{
+    constexpr int D = 4;
+    constexpr int NP = packed_floats(D);
+    constexpr int NM = state_floats(D);  // model entries; the history follows
+    constexpr int NS = NM + 3;
+    const uint32_t n = (uint32_t)a.W * (uint32_t)a.H;
+    const uint32_t j = (uint32_t)y * (uint32_t)a.W + (uint32_t)x;
+    const InT *tag = nullptr;
+    const Rsrc r_color = array_rsrc(a.color, 3u * n * (uint32_t)sizeof(InT));
+
+    float yc[3];
+#pragma unroll
+    for (int c = 0; c < 3; c++) yc[c] = load_in(r_color, tag, n, c, j);
+    const bool ok = finite(yc[0]) && finite(yc[1]) && finite(yc[2]);
+
+    float st[NS];
+    const bool have = gather_state<NS>(a, x, y, j, n, st);
+    if (!have) init_model<D>(a.p0, st, st + NP);
+    float z[3];
+    if (ok) {
+        // Eq. 12: history clamped to the current colour's range over the 3x3
+        // neighbourhood (inside the image, finite values), blended with the
+        // current colour; without history z is the colour itself.
+        float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
         if (have) {
-            const uint32_t pbytes = (uint32_t)a.pitch * 4u;
-            const Rsrc src = array_rsrc(a.state_in, (uint32_t)(NP + NB) * pbytes);
-            if (a.nearest) {
-                const int xn = min((int)floorf(sx + 0.5f), a.W - 1);
-                const int yn = min((int)floorf(sy + 0.5f), a.H - 1);
-                const uint32_t o = ((uint32_t)yn * (uint32_t)a.W + (uint32_t)xn) * 4u;
 #pragma unroll
-                for (int k = 0; k < NP; k++) P[k] = bload(src, o, (uint32_t)k * pbytes);
+            for (int dy = -1; dy <= 1; dy++)
 #pragma unroll
-                for (int k = 0; k < NB; k++) B[k] = bload(src, o, (uint32_t)(NP + k) * pbytes);
-            } else {
-                const float fx0 = floorf(sx), fy0 = floorf(sy);
-                const float fx = sx - fx0, fy = sy - fy0;
-                const int x0 = (int)fx0, y0 = (int)fy0;
-                const int x1 = min(x0 + 1, a.W - 1), y1 = min(y0 + 1, a.H - 1);
-                const uint32_t W = (uint32_t)a.W;
-                const uint32_t o00 = ((uint32_t)y0 * W + (uint32_t)x0) * 4u;
-                const uint32_t o10 = ((uint32_t)y0 * W + (uint32_t)x1) * 4u;
-                const uint32_t o01 = ((uint32_t)y1 * W + (uint32_t)x0) * 4u;
-                const uint32_t o11 = ((uint32_t)y1 * W + (uint32_t)x1) * 4u;
-                // Bilinear in nested-lerp form (exact for a constant field).
-                // Planes go in groups of kGatherGroup: the group's 4 * kGatherGroup
-                // loads are issued back to back, so many are in flight per wave,
-                // before any of them is consumed.
+                for (int dx = -1; dx <= 1; dx++) {
+                    const int nx = x + dx, ny = y + dy;
+                    if (nx < 0 || ny < 0 || nx >= a.W || ny >= a.H) continue;
+                    const uint32_t jn = (uint32_t)ny * (uint32_t)a.W + (uint32_t)nx;
 #pragma unroll
-                for (int k0 = 0; k0 < NP + NB; k0 += kGatherGroup) {
-                    float t00[kGatherGroup], t10[kGatherGroup], t01[kGatherGroup], t11[kGatherGroup];
-#pragma unroll
-                    for (int g = 0; g < kGatherGroup; g++) {
-                        if (k0 + g < NP + NB) {
-                            const uint32_t so = (uint32_t)(k0 + g) * pbytes;
-                            t00[g] = bload(src, o00, so);
-                            t10[g] = bload(src, o10, so);
-                            t01[g] = bload(src, o01, so);
-                            t11[g] = bload(src, o11, so);
-                        }
-                    }
-                    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                    for (int g = 0; g < kGatherGroup; g++) {
-                        const int k = k0 + g;
-                        if (k < NP + NB) {
-                            const float top = fmaf(fx, t10[g] - t00[g], t00[g]);
-                            const float bot = fmaf(fx, t11[g] - t01[g], t01[g]);
-                            const float v = fmaf(fy, bot - top, top);
-                            if (k < NP) P[k] = v; else B[k - NP] = v;
+                    for (int c = 0; c < 3; c++) {
+                        const float v = load_in(r_color, tag, n, c, jn);
+                        if (finite(v)) {
+                            lo[c] = fminf(lo[c], v);
+                            hi[c] = fmaxf(hi[c], v);
                         }
                     }
                 }
-            }
         }
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            const float psi = fminf(fmaxf(st[NM + c], lo[c]), hi[c]);
+            z[c] = have ? fmaf(a.alpha, psi, (1.0f - a.alpha) * yc[c]) : yc[c];
+        }
+    } else {
+        // no usable sample: the history is carried unchanged
+#pragma unroll
+        for (int c = 0; c < 3; c++) z[c] = have ? st[NM + c] : 0.0f;
     }
-    if (!have) {
+    float w = 0.0f;
+    if (ok) {
+        // Eq. 13: w = exp(-dist^2 / h^2), dist = |I - z| / (min(|I|, |z|) + eps)
+        float dd = 0.0f, ny = 0.0f, nz = 0.0f;
 #pragma unroll
-        for (int i = 0; i < D; i++)
-#pragma unroll
-            for (int m = i; m < D; m++) P[packed_index(D, i, m)] = (i == m) ? a.p0 : 0.0f;
-#pragma unroll
-        for (int k = 0; k < NB; k++) B[k] = 0.0f;
+        for (int c = 0; c < 3; c++) {
+            const float e = yc[c] - z[c];
+            dd = fmaf(e, e, dd);
+            ny = fmaf(yc[c], yc[c], ny);
+            nz = fmaf(z[c], z[c], nz);
+        }
+        const float dist = sqrtf(dd) / (fminf(sqrtf(ny), sqrtf(nz)) + a.eps);
+        w = expf(-(dist * dist) * a.inv_h2);
     }
-
-    // Gain (Eq. 14, multiplied through by w): k = P p^T, s = p k,
-    // q = g k with g = w / (lambda + w s); g = 0 when w = 0.
-    float kv[D];
-#pragma unroll
-    for (int i = 0; i < D; i++) {
-        float acc = 0.0f;
-#pragma unroll
-        for (int m = 0; m < D; m++)
-            acc = fmaf(P[i <= m ? packed_index(D, i, m) : packed_index(D, m, i)], p[m], acc);
-        kv[i] = acc;
-    }
-    float s = 0.0f;
-#pragma unroll
-    for (int i = 0; i < D; i++) s = fmaf(p[i], kv[i], s);
-    const float g = w / fmaf(w, s, a.lambda);
-
-    // Residual against the previous coefficients (Eq. 8) and update (Eq. 9),
-    // then the a-posteriori prediction (Eq. 6).
+    const float p[D] = {1.0f, z[0], z[1], z[2]};
     float out[3];
+    rls_update<D>(st, st + NP, p, yc, w, ok, a.lambda, a.inv_lambda, out);
 #pragma unroll
-    for (int c = 0; c < 3; c++) {
-        float pred = 0.0f;
-#pragma unroll
-        for (int i = 0; i < D; i++) pred = fmaf(p[i], B[c * D + i], pred);
-        const float ge = ok ? g * (yc[c] - pred) : 0.0f;
-        float post = 0.0f;
-#pragma unroll
-        for (int i = 0; i < D; i++) {
-            B[c * D + i] = fmaf(ge, kv[i], B[c * D + i]);
-            post = fmaf(p[i], B[c * D + i], post);
-        }
-        out[c] = post;
-    }
-
-    // Inverse covariance (Eq. 11): P <- (P - g k k^T) / lambda on the upper
-    // triangle; symmetric by construction.
-#pragma unroll
-    for (int i = 0; i < D; i++) {
-        const float gki = g * kv[i];
-#pragma unroll
-        for (int m = i; m < D; m++) {
-            const int idx = packed_index(D, i, m);
-            P[idx] = fmaf(-gki, kv[m], P[idx]) * a.inv_lambda;
-        }
-    }
-
-    const uint32_t pbytes = (uint32_t)a.pitch * 4u;
-    const Rsrc dst = array_rsrc(a.state_out, (uint32_t)(NP + NB) * pbytes);
-    const Rsrc r_out = array_rsrc(a.out, 3u * n * 4u);
-    const uint32_t oj = j * 4u;
-#pragma unroll
-    for (int k = 0; k < NP; k++) bstore(dst, oj, (uint32_t)k * pbytes, P[k]);
-#pragma unroll
-    for (int k = 0; k < NB; k++) bstore(dst, oj, (uint32_t)(NP + k) * pbytes, B[k]);
-#pragma unroll
-    for (int c = 0; c < 3; c++) bstore(r_out, oj, (uint32_t)c * n * 4u, out[c]);
+    for (int c = 0; c < 3; c++) st[NM + c] = z[c];
+    store_pixel<NS>(a, j, n, st, out);
 }
 
 // Tile order: the image is cut into vertical strips of strip_w tiles (the
@@ -291,12 +393,25 @@ __global__ void __launch_bounds__(256) step_kernel(const FrameArgs a, const Tile
     update_pixel<D, InT>(a, x, y);
 }
 
-// Initial state: P = p0 * I (p0 = 1 / delta), beta = 0, every pixel.
+template <typename InT>
+__global__ void __launch_bounds__(256) paper_step_kernel(const FrameArgs a, const TileShape ts)
+{
+    const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    int tx, ty;
+    tile_coords(tile, a.tiles_x, a.tiles_y, a.strip_w, tx, ty);
+    const int tw_mask = (1 << ts.tw_log2) - 1;
+    const int x = (tx << ts.tw_log2) + ((int)threadIdx.x & tw_mask);
+    const int y = ty * (ts.block_threads >> ts.tw_log2) + ((int)threadIdx.x >> ts.tw_log2);
+    if (x >= a.W || y >= a.H) return;
+    update_pixel_paper<InT>(a, x, y);
+}
+
+// Initial state: P = p0 * I (p0 = 1 / delta), beta = 0 (and a zero history
+// in paper mode: S = state_floats(d) + 3), every pixel.
 __global__ void __launch_bounds__(256) reset_kernel(float *state, int64_t pitch, int64_t npix,
-                                                    int d, float p0)
+                                                    int d, int S, float p0)
 {
     const int np = packed_floats(d);
-    const int S = state_floats(d);
     const int64_t total = (int64_t)S * npix;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
@@ -404,16 +519,36 @@ hipError_t launch_batched_d(bool f16, const BatchTable *tab, int32_t grid, int32
 
 }  // namespace
 
-hipError_t launch_reset(float *state, int64_t pitch, int64_t npix, int d, float p0,
+hipError_t launch_reset(float *state, int64_t pitch, int64_t npix, int d, int S, float p0,
                         hipStream_t st)
 {
     (void)hipGetLastError();  // report this launch's error, not an older one
-    const int64_t total = (int64_t)state_floats(d) * npix;
+    const int64_t total = (int64_t)S * npix;
     int64_t blocks = (total + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(reset_kernel, dim3((unsigned)blocks), dim3(256), 0, st, state, pitch, npix,
-                       d, p0);
+                       d, S, p0);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_paper(bool f16, const FrameArgs &a, TileShape ts, hipStream_t st)
+{
+    const int tw = 1 << ts.tw_log2;
+    const int th = ts.block_threads >> ts.tw_log2;
+    const int tiles_x = (a.W + tw - 1) / tw;
+    const int tiles_y = (a.H + th - 1) / th;
+    FrameArgs b = a;
+    (void)hipGetLastError();  // report this launch's error, not an older one
+    b.tiles_x = tiles_x;
+    b.tiles_y = tiles_y;
+    const int strip_w = ts.strip_w <= 0 ? tiles_x : ts.strip_w;
+    b.strip_w = strip_w > tiles_x ? tiles_x : strip_w;
+    const dim3 grid((unsigned)(tiles_x * tiles_y)), block((unsigned)ts.block_threads);
+    if (f16)
+        hipLaunchKernelGGL((paper_step_kernel<_Float16>), grid, block, 0, st, b, ts);
+    else
+        hipLaunchKernelGGL((paper_step_kernel<float>), grid, block, 0, st, b, ts);
     return hipGetLastError();
 }
 

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libwrls.so")
 
 WRLS_OK, WRLS_EINVAL, WRLS_ENOMEM, WRLS_EHIP, WRLS_EUNSUPPORTED = 0, -1, -2, -3, -4
 WRLS_F32, WRLS_F16 = 0, 1
-WRLS_W_INVVAR, WRLS_W_ONE = 0, 1
+WRLS_W_INVVAR, WRLS_W_ONE, WRLS_W_PAPER = 0, 1, 2
 WRLS_INTERP_BILINEAR, WRLS_INTERP_NEAREST = 0, 1
 WRLS_MAX_D = 10
 
@@ -36,7 +36,8 @@ class wrls_params(ctypes.Structure):
                 ("lambda_", ctypes.c_float), ("delta", ctypes.c_float),
                 ("var_floor", ctypes.c_float), ("in_dtype", ctypes.c_int32),
                 ("weight_mode", ctypes.c_int32), ("interp", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 3)]
+                ("alpha", ctypes.c_float), ("h", ctypes.c_float), ("eps", ctypes.c_float),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class wrls_frame(ctypes.Structure):
@@ -67,6 +68,8 @@ SIGNATURES = {
     "wrls_step": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP]),
     "wrls_get_state": (ctypes.c_int, [_VP, _VP, _VP]),
     "wrls_set_state": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int64]),
+    "wrls_get_history": (ctypes.c_int, [_VP, _VP]),
+    "wrls_set_history": (ctypes.c_int, [_VP, _VP]),
     "wrls_batch_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _VP,
                                          ctypes.POINTER(_VP)]),
     "wrls_batch_destroy": (ctypes.c_int, [_VP]),
@@ -226,6 +229,14 @@ def wrls_batch_step(b: int, handles, frames):
     _check(lib().wrls_batch_step(b, n, hs, fs))
 
 
+def wrls_get_history(h: int, z):
+    _check(lib().wrls_get_history(h, _ptr(z)))
+
+
+def wrls_set_history(h: int, z):
+    _check(lib().wrls_set_history(h, _ptr(z)))
+
+
 def wrls_last_error() -> str:
     return lib().wrls_last_error().decode(errors="replace")
 
@@ -237,15 +248,17 @@ def wrls_version() -> str:
 # ---- convenience wrapper over torch tensors -------------------------------
 
 _DTYPES = {"f32": WRLS_F32, "f16": WRLS_F16}
-_WMODES = {"invvar": WRLS_W_INVVAR, "one": WRLS_W_ONE}
+_WMODES = {"invvar": WRLS_W_INVVAR, "one": WRLS_W_ONE, "paper": WRLS_W_PAPER}
 _INTERPS = {"bilinear": WRLS_INTERP_BILINEAR, "nearest": WRLS_INTERP_NEAREST}
 
 
 def make_params(width, height, d, lam=0.98, delta=1.0, var_floor=1e-6, in_dtype="f32",
-                weight_mode="invvar", interp="bilinear") -> wrls_params:
+                weight_mode="invvar", interp="bilinear", alpha=0.75, h=0.75,
+                eps=1e-4) -> wrls_params:
     p = wrls_params_default(width, height, d)
     p.lambda_, p.delta, p.var_floor = lam, delta, var_floor
     p.in_dtype, p.weight_mode, p.interp = _DTYPES[in_dtype], _WMODES[weight_mode], _INTERPS[interp]
+    p.alpha, p.h, p.eps = alpha, h, eps
     return p
 
 
@@ -260,12 +273,17 @@ class Stream:
     def __init__(self, width: int, height: int, d: int, lam: float = 0.98, delta: float = 1.0,
                  var_floor: float = 1e-6, in_dtype: str = "f32", weight_mode: str = "invvar",
                  interp: str = "bilinear", hip_stream: Optional[int] = None,
-                 device_mem: Optional[Tuple[int, int]] = None):
+                 device_mem: Optional[Tuple[int, int]] = None, alpha: float = 0.75,
+                 h: float = 0.75, eps: float = 1e-4):
         """device_mem: (pointer, bytes) of caller-owned device memory for the
-        state (wrls_create_stream_in); None: the library allocates."""
+        state (wrls_create_stream_in); None: the library allocates.
+        weight_mode "paper" (d = 4): the paper's predictor and weight
+        (alpha, h, eps); features and variance are then not used."""
         import torch
         self._torch = torch
-        p = make_params(width, height, d, lam, delta, var_floor, in_dtype, weight_mode, interp)
+        p = make_params(width, height, d, lam, delta, var_floor, in_dtype, weight_mode, interp,
+                        alpha, h, eps)
+        self.paper = weight_mode == "paper"
         self.params = p
         self.W, self.H, self.d = width, height, d
         self.in_dtype = torch.float16 if in_dtype == "f16" else torch.float32
@@ -303,14 +321,15 @@ class Stream:
         torch = self._torch
         W, H, d = self.W, self.H, self.d
         self._chk(color, (3, H, W), self.in_dtype, "color")
-        if d > 1:
+        if d > 1 and not self.paper:
             self._chk(features, (d - 1, H, W), self.in_dtype, "features")
         self._chk(variance, (H, W), torch.float32, "variance")
         self._chk(motion, (2, H, W), torch.float32, "motion")
         if out is None:
             out = torch.empty((3, H, W), dtype=torch.float32, device=color.device)
         self._chk(out, (3, H, W), torch.float32, "out")
-        wrls_step(self.handle, color, features if d > 1 else None, variance, motion, out)
+        wrls_step(self.handle, color, features if (d > 1 and not self.paper) else None, variance,
+                  motion, out)
         return out
 
     def reset(self):
@@ -330,6 +349,16 @@ class Stream:
         B = torch.empty((3, d, H, W), dtype=torch.float32, device="cuda")
         wrls_get_state(self.handle, P, B)
         return P, B
+
+    def get_history(self):
+        """Paper mode: the temporal feature history z, (3, H, W)."""
+        z = self._torch.empty((3, self.H, self.W), dtype=self._torch.float32, device="cuda")
+        wrls_get_history(self.handle, z)
+        return z
+
+    def set_history(self, z):
+        self._chk(z, (3, self.H, self.W), self._torch.float32, "z")
+        wrls_set_history(self.handle, z)
 
     def set_state(self, P_packed, beta, frames: int = 1):
         torch = self._torch

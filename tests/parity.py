@@ -95,38 +95,79 @@ def to_dev(a: np.ndarray):
 
 
 class Pair:
-    """A GPU stream and an oracle fed identical frames."""
+    """A GPU stream and an oracle fed identical frames.  weight_mode "paper"
+    (d = 4) runs the paper's temporal feature and weight on both sides; the
+    predictor of the error measures is then [1, z] with the oracle's z."""
 
     def __init__(self, W, H, d, lam=0.98, delta=1.0, var_floor=1e-6, in_dtype="f32",
-                 weight_mode="invvar", interp="bilinear"):
+                 weight_mode="invvar", interp="bilinear", alpha=0.75, h=0.75, eps=1e-4):
         import oracle
         from paper_2106_08034_amd import wrls
+        # both sides take the binary32 values of the paper-mode constants
+        alpha, h, eps = (float(np.float32(v)) for v in (alpha, h, eps))
         self.gpu = wrls.Stream(W, H, d, lam=lam, delta=delta, var_floor=var_floor,
-                               in_dtype=in_dtype, weight_mode=weight_mode, interp=interp)
+                               in_dtype=in_dtype, weight_mode=weight_mode, interp=interp,
+                               alpha=alpha, h=h, eps=eps)
         self.ref = oracle.Oracle(W, H, d, lam=lam, delta=delta, var_floor=var_floor,
-                                 wmode={"invvar": oracle.W_INVVAR, "one": oracle.W_ONE}[weight_mode],
+                                 wmode={"invvar": oracle.W_INVVAR, "one": oracle.W_ONE,
+                                        "paper": oracle.W_PAPER}[weight_mode],
                                  interp={"bilinear": oracle.INTERP_BILINEAR,
-                                         "nearest": oracle.INTERP_NEAREST}[interp])
+                                         "nearest": oracle.INTERP_NEAREST}[interp],
+                                 alpha=alpha, h_bw=h, eps=eps)
         self.d = d
+        self.paper = weight_mode == "paper"
+        self.alpha = alpha
+        self._z_prev = self._motion = None
+
+    def _p(self, feats, shape):
+        if self.paper:
+            return predictor(self.ref.get_history())
+        p = predictor(feats) if self.d > 1 else np.ones((1,) + shape)
+        # non-finite predictor entries enter the model as 0 (weight-0 frames)
+        return np.where(np.isfinite(p), p, 0.0)
 
     def step(self, color, feats, var, motion):
         """One frame on both sides: (gpu output, oracle output, G1 error)."""
-        out = self.gpu.step(to_dev(color), to_dev(feats) if self.d > 1 else None,
+        if self.paper:
+            self._z_prev = self.ref.get_history() if self.ref.frames > 0 else None
+            self._motion = motion
+        use_f = self.d > 1 and not self.paper
+        out = self.gpu.step(to_dev(color), to_dev(feats) if use_f else None,
                             None if var is None else to_dev(var),
                             None if motion is None else to_dev(motion))
-        ref = self.ref.step(color, feats if self.d > 1 else None, var, motion)
-        p = predictor(feats) if self.d > 1 else np.ones((1,) + ref.shape[1:])
-        # non-finite predictor entries enter the model as 0 (weight-0 frames)
-        p = np.where(np.isfinite(p), p, 0.0)
-        scale = term_scale(self.ref.get_beta(), p)
+        ref = self.ref.step(color, feats if use_f else None, var, motion)
+        scale = term_scale(self.ref.get_beta(), self._p(feats, ref.shape[1:]))
         out = out.cpu().numpy()
         return out, ref, g1(out, ref, scale)
+
+    def history_error(self) -> float:
+        """Paper mode: max |z_gpu - z_ref| / max(|z_ref|, s_z, tau) of the
+        history after the last step, where s_z = alpha * max |z_prev| over the
+        2x2 source pixels of the pixel's reprojection.  z is a clamp and a
+        blend of the bilinear sum sum_k w_k z_prev,k, whose binary32 rounding
+        is proportional to the magnitude of its terms (bounded by s_z), not to
+        |z|: a dark pixel next to bright ones carries the bright ones' ulp."""
+        zg = self.gpu.get_history().cpu().numpy()
+        zr = self.ref.get_history()
+        scale = np.zeros_like(zr)
+        if self._z_prev is not None:
+            H, W = zr.shape[1:]
+            mv = np.zeros((2, H, W), np.float32) if self._motion is None else self._motion
+            sx = np.arange(W, dtype=np.float32)[None, :] + mv[0]
+            sy = np.arange(H, dtype=np.float32)[:, None] + mv[1]
+            inside = np.isfinite(sx) & np.isfinite(sy) & (sx >= 0) & (sx <= W - 1) & (sy >= 0) & (sy <= H - 1)
+            x0 = np.where(inside, np.floor(np.where(inside, sx, 0)), 0).astype(np.int64)
+            y0 = np.where(inside, np.floor(np.where(inside, sy, 0)), 0).astype(np.int64)
+            x1, y1 = np.minimum(x0 + 1, W - 1), np.minimum(y0 + 1, H - 1)
+            a = np.abs(self._z_prev)
+            m = np.maximum(np.maximum(a[:, y0, x0], a[:, y0, x1]), np.maximum(a[:, y1, x0], a[:, y1, x1]))
+            scale = np.where(inside[None], self.alpha * m, 0.0)
+        return g1(zg, zr, scale)
 
     def state_errors(self, last_feats):
         """(G2, G3, normwise beta error) of the current state."""
         Pg, Bg = self.gpu.get_state()
         Pr, Br = self.ref.get_state()
         Pg, Bg = Pg.cpu().numpy(), Bg.cpu().numpy()
-        p = predictor(last_feats) if self.d > 1 else np.ones((1,) + Pr.shape[2:])
-        p = np.where(np.isfinite(p), p, 0.0)
+        p = self._p(last_feats, Pr.shape[2:])
         return g2(Pg, Pr), g3(Bg, Br, p), beta_normwise(Bg, Br)

@@ -87,6 +87,27 @@ def test_state_copy_limit_4gib():
     assert wrls.wrls_params_validate(wrls.wrls_params_default(side + 64, side + 64, 10)) == wrls.WRLS_EUNSUPPORTED
 
 
+def test_paper_mode_parameters():
+    p = wrls.wrls_params_default(64, 48, 4)
+    assert abs(p.alpha - 0.75) < 1e-7 and abs(p.h - 0.75) < 1e-7 and abs(p.eps - 1e-4) < 1e-9
+    p.weight_mode = wrls.WRLS_W_PAPER
+    assert wrls.wrls_params_validate(p) == wrls.WRLS_OK
+    # the history adds 3 entries per pixel
+    assert wrls.wrls_state_bytes(p) == (10 + 12 + 3) * 4 * 64 * 48
+    p.d = 8
+    assert wrls.wrls_params_validate(p) == wrls.WRLS_EINVAL and "d = 4" in wrls.wrls_last_error()
+    p.d = 4
+    for field, bad in (("alpha", 1.5), ("alpha", -0.1), ("h", 0.0), ("h", float("inf")), ("h", 1e-25),
+                       ("eps", -1.0), ("eps", 0.0), ("eps", float("nan"))):
+        q = wrls.wrls_params_default(64, 48, 4)
+        q.weight_mode = wrls.WRLS_W_PAPER
+        setattr(q, field, bad)
+        assert wrls.wrls_params_validate(q) == wrls.WRLS_EINVAL, (field, bad)
+    L = wrls.lib()
+    assert L.wrls_get_history(None, None) == wrls.WRLS_EINVAL
+    assert L.wrls_set_history(None, None) == wrls.WRLS_EINVAL
+
+
 def test_reserved_must_be_zero():
     p = wrls.wrls_params_default(8, 8, 8)
     p.reserved[1] = 1
