@@ -33,6 +33,15 @@ def algorithmic_bytes_per_pixel(d: int, in_bytes: int, motion: bool = True) -> i
     return inputs + 4 * S + 4 * S + 12
 
 
+def algorithmic_bytes_per_pixel_paper(in_bytes: int, motion: bool = True) -> int:
+    """Paper mode (d = 4, p = [1, z]): colour in the input type, FP32 motion,
+    the previous state (P 10, beta 12, history z 3 floats) read once, the new
+    state written once, and the FP32 output.  The 3x3 colour neighbourhood of
+    the clamp is counted once: its other reads hit the caches."""
+    S = 10 + 12 + 3
+    return 3 * in_bytes + (8 if motion else 0) + 4 * S + 4 * S + 12
+
+
 def kernel_source_hash() -> str:
     src = os.path.join(ROOT, "paper_2106_08034_amd", "csrc", "wrls_kernels.hip")
     return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
@@ -58,6 +67,8 @@ def make_workload(name: str):
         return synth.c3()
     if name == "c1":
         return synth.c1()
+    if name == "c2p":
+        return synth.c2()   # the same scene, run in paper mode
     raise SystemExit("unknown workload %r" % name)
 
 
@@ -212,7 +223,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=60)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c2p", "c3", "c4", "c5"],
+                    help="c2p: the c2 scene with the paper's own predictor and weight "
+                         "(Eq. 12-13, d = 4)")
     ap.add_argument("--serve-seconds", type=float, default=15.0,
                     help="c5 (and the default run's serving leg): wall seconds of serving")
     ap.add_argument("--budget-gb", type=float, default=0.0,
@@ -276,6 +289,8 @@ def main():
         print(json.dumps(line), flush=True)
         return
     wl = make_workload(args.workload)
+    paper = args.workload == "c2p"
+    d_model = 4 if paper else wl.d
     t0 = time.time()
     src = synth.FrameSource(wl)
     host_frames = []
@@ -283,12 +298,17 @@ def main():
     for t in range(wl.frames):
         f = src.next()
         host_frames.append(f)
-        dev_frames.append(tuple(torch.from_numpy(a).to(dev) for a in (f.color, f.feats, f.var, f.motion)))
+        up = lambda a: torch.from_numpy(a).to(dev)
+        if paper:  # features and variance are not inputs of paper mode
+            dev_frames.append((up(f.color), None, None, up(f.motion)))
+        else:
+            dev_frames.append(tuple(up(a) for a in (f.color, f.feats, f.var, f.motion)))
     torch.cuda.synchronize()
     print("generated and uploaded %d frames of %s in %.1fs" % (wl.frames, wl.name, time.time() - t0),
           file=sys.stderr, flush=True)
 
-    stream = wrls.Stream(wl.width, wl.height, wl.d, lam=0.98, in_dtype=wl.in_dtype)
+    stream = wrls.Stream(wl.width, wl.height, d_model, lam=0.98, in_dtype=wl.in_dtype,
+                         weight_mode="paper" if paper else "invvar")
     out = torch.empty((3, wl.height, wl.width), dtype=torch.float32, device=dev)
     cs = torch.cuda.current_stream()
 
@@ -311,7 +331,10 @@ def main():
     npix = wl.width * wl.height
     mpix_s = K * npix / elapsed / 1e6
     in_bytes = 2 if wl.in_dtype == "f16" else 4
-    bpp = algorithmic_bytes_per_pixel(wl.d, in_bytes, motion=wl.motion != "static")
+    if paper:
+        bpp = algorithmic_bytes_per_pixel_paper(in_bytes, motion=wl.motion != "static")
+    else:
+        bpp = algorithmic_bytes_per_pixel(wl.d, in_bytes, motion=wl.motion != "static")
     avg_launch_s = float(np.mean(per_launch_ms)) / 1e3
     achieved_gbs = bpp * npix / avg_launch_s / 1e9
     traffic = load_traffic(args.workload)
@@ -326,9 +349,15 @@ def main():
         frames_done = 0
         tc = time.perf_counter()
         while passes < 8 and (passes == 0 or time.perf_counter() - tc < 10.0):
-            o = oracle.Oracle(wl.width, wl.height, wl.d, lam=0.98)
+            if paper:
+                o = oracle.Oracle(wl.width, wl.height, 4, lam=0.98, wmode=oracle.W_PAPER)
+            else:
+                o = oracle.Oracle(wl.width, wl.height, wl.d, lam=0.98)
             for f in host_frames[:n_cpu]:
-                o.step(f.color, f.feats, f.var, f.motion)
+                if paper:
+                    o.step(f.color, None, None, f.motion)
+                else:
+                    o.step(f.color, f.feats, f.var, f.motion)
             del o
             passes += 1
             frames_done += n_cpu
@@ -351,13 +380,14 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if wl.in_dtype == "f32" else "f32 (f16 inputs)",
         "data": "synthetic (seeded procedural scene, lognormal per-pixel noise variance)",
-        "config": {"workload": wl.name, "width": wl.width, "height": wl.height, "d": wl.d,
+        "config": {"workload": wl.name + ("-paper-mode-d4" if paper else ""),
+                   "width": wl.width, "height": wl.height, "d": d_model,
                    "frames_in_sequence": wl.frames, "lambda": 0.98,
                    "input_dtype": wl.in_dtype, "state_dtype": "f32"},
         "roofline": {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
-                     "kernel": "wrls step_kernel<%d>" % wl.d,
+                     "kernel": "wrls paper_step_kernel" if paper else "wrls step_kernel<%d>" % wl.d,
                      "algorithmic_bytes_per_pixel": bpp,
                      "avg_launch_us": round(avg_launch_s * 1e6, 2),
                      "launch_us_min_max": [round(min(per_launch_ms) * 1e3, 2),
