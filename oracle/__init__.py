@@ -74,6 +74,8 @@ def _load():
     lib.oracle_get_state.argtypes = [ctypes.c_void_p, dp, dp]
     lib.oracle_get_beta.argtypes = [ctypes.c_void_p, dp]
     lib.oracle_set_state.argtypes = [ctypes.c_void_p, dp, dp, ctypes.c_long]
+    lib.oracle_blend.restype = ctypes.c_int
+    lib.oracle_blend.argtypes = [ctypes.c_void_p, dp, ctypes.c_double, ctypes.c_double, dp]
     _lib = lib
     return lib
 
@@ -157,6 +159,19 @@ class Oracle:
         if rc != 0:
             raise ValueError("oracle_step rejected the region %r" % (roi,))
         return (out, prior) if want_prior else out
+
+    def blend(self, feats, sigma_s, sigma_r):
+        """The 5x5 spatial blend of neighbour-model predictions (Sec. 5.3) on
+        the current state: feats (d-1,H,W) of the frame just stepped (None
+        in paper mode); sigma_s in pixels, sigma_r in colour units (+inf
+        turns a factor off).  Returns (3,H,W) float64."""
+        W, H, d = self.W, self.H, self.d
+        f = _f64(feats, (d - 1, H, W)) if (d > 1 and feats is not None) else None
+        out = np.zeros((3, H, W), np.float64)
+        rc = self._lib.oracle_blend(self._h, _ptr(f), float(sigma_s), float(sigma_r), _ptr(out))
+        if rc != 0:
+            raise ValueError("oracle_blend: no state yet, or features missing")
+        return out
 
     def get_state(self):
         """(P, beta): P (d,d,H,W) full matrices, beta (3,d,H,W)."""

@@ -42,6 +42,12 @@
  *   w = exp(-dist^2 / h^2),  dist = |I~ - z| / (min(|I~|, |z|) + eps)  (Eq. 13)
  * with Euclidean norms over the three channels.
  *
+ * Spatial blend (Sec. 5.3, last paragraph), a separate pass after a step:
+ * the final colour of pixel i averages, over the 5x5 window centred on i,
+ * the predictions p_i beta_k^T that the neighbours' models make for pixel i,
+ * with a bilateral weight (Gaussian in pixel distance times Gaussian in the
+ * distance between the neighbours' temporal outputs).
+ *
  * Parity pins: closed-form exponentially weighted least squares, the d = 1
  * weighted mean, brute-force stacked design matrices (Eq. 7), SPD and
  * symmetry of P, the noise-free identities, exact integer shifts and exact
@@ -470,4 +476,82 @@ void oracle_set_state(oracle *o, const double *P, const double *beta, long frame
         for (int i = 0; i < 3 * d; i++) o->beta_cur[j * 3 * d + i] = beta[(size_t)i * n + j];
     }
     o->frames = frames;
+}
+
+/* The predictor of pixel j for the blend: [1, features] or, in paper mode,
+ * [1, z] with the stored history.  Non-finite entries enter as 0, as they
+ * do in the step's output. */
+static void blend_predictor(const oracle *o, const double *feats, size_t j, double *p)
+{
+    size_t n = npix(o);
+    p[0] = 1.0;
+    for (int i = 1; i < o->d; i++) {
+        double v = o->wmode == ORACLE_W_PAPER ? o->z_cur[j * 3 + (size_t)(i - 1)]
+                                              : feats[(size_t)(i - 1) * n + j];
+        p[i] = isfinite(v) ? v : 0.0;
+    }
+}
+
+/*
+ * Spatial blend of neighbour-model predictions (Sec. 5.3, last paragraph)
+ * on the current state.  For each pixel i, over the pixels k of the 5x5
+ * window centred on i that lie inside the image:
+ *   out_i = sum_k w_ik (p_i beta_k^T) / sum_k w_ik,
+ *   w_ik  = exp(-|x_k - x_i|^2 / (2 sigma_s^2)) * exp(-|yhat_k - yhat_i|^2 / (2 sigma_r^2)),
+ * where yhat_k = p_k beta_k^T is the temporal output of pixel k (Eq. 6) and
+ * |.| is the Euclidean norm (pixels; RGB).  sigma = +inf turns its factor
+ * off.  feats: the features of the frame just stepped ((d-1) planes; unused
+ * in paper mode).  out: planar [3][H][W].  Returns -1 before the first step
+ * or without features.
+ */
+int oracle_blend(const oracle *o, const double *feats, double sigma_s, double sigma_r, double *out)
+{
+    int W = o->W, H = o->H, d = o->d;
+    size_t n = npix(o);
+    if (o->frames == 0) return -1;
+    if (o->wmode != ORACLE_W_PAPER && d > 1 && !feats) return -1;
+    double *yhat = malloc(n * 3 * sizeof(double));
+    if (!yhat) return -1;
+    for (size_t j = 0; j < n; j++) {
+        double p[32];
+        blend_predictor(o, feats, j, p);
+        for (int c = 0; c < 3; c++) {
+            double acc = 0.0;
+            for (int m = 0; m < d; m++) acc += p[m] * o->beta_cur[j * 3 * d + (size_t)c * d + m];
+            yhat[j * 3 + c] = acc;
+        }
+    }
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int y = 0; y < H; y++) {
+        for (int x = 0; x < W; x++) {
+            size_t i = (size_t)y * W + x;
+            double p[32], num[3] = {0.0, 0.0, 0.0}, den = 0.0;
+            blend_predictor(o, feats, i, p);
+            for (int dy = -2; dy <= 2; dy++) {
+                for (int dx = -2; dx <= 2; dx++) {
+                    int nx = x + dx, ny = y + dy;
+                    if (nx < 0 || ny < 0 || nx >= W || ny >= H) continue;
+                    size_t k = (size_t)ny * W + nx;
+                    double ds2 = (double)(dx * dx + dy * dy);
+                    double dr2 = 0.0;
+                    for (int c = 0; c < 3; c++) {
+                        double e = yhat[k * 3 + c] - yhat[i * 3 + c];
+                        dr2 += e * e;
+                    }
+                    double w = exp(-ds2 / (2.0 * sigma_s * sigma_s)) *
+                               exp(-dr2 / (2.0 * sigma_r * sigma_r));
+                    for (int c = 0; c < 3; c++) {
+                        double pred = 0.0;  /* neighbour k's model at pixel i */
+                        for (int m = 0; m < d; m++)
+                            pred += p[m] * o->beta_cur[k * 3 * d + (size_t)c * d + m];
+                        num[c] += w * pred;
+                    }
+                    den += w;
+                }
+            }
+            for (int c = 0; c < 3; c++) out[(size_t)c * n + i] = num[c] / den;
+        }
+    }
+    free(yhat);
+    return 0;
 }

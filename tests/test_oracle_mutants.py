@@ -51,6 +51,22 @@ MUTANTS = {
                                      "              + fx * (1.0 - fy) * o->z_prev[((size_t)y0 * W + x0) * 3 + c]"),
     "history_not_carried": ("                    for (int c = 0; c < 3; c++) z[c] = zq[c];",
                             "                    for (int c = 0; c < 3; c++) z[c] = 0.0;"),
+    # spatial blend (Sec. 5.3, last paragraph)
+    "blend_window_3x3": ("for (int dy = -2; dy <= 2; dy++) {\n                for (int dx = -2; dx <= 2; dx++) {",
+                         "for (int dy = -1; dy <= 1; dy++) {\n                for (int dx = -1; dx <= 1; dx++) {"),
+    "blend_spatial_no_half": ("exp(-ds2 / (2.0 * sigma_s * sigma_s))", "exp(-ds2 / (sigma_s * sigma_s))"),
+    "blend_range_no_half": ("exp(-dr2 / (2.0 * sigma_r * sigma_r))", "exp(-dr2 / (sigma_r * sigma_r))"),
+    "blend_range_dropped": ("exp(-dr2 / (2.0 * sigma_r * sigma_r))", "1.0"),
+    "blend_range_l1": ("                        dr2 += e * e;", "                        dr2 += fabs(e);"),
+    "blend_neighbour_predictor": ("                            pred += p[m] * o->beta_cur[k * 3 * d + (size_t)c * d + m];",
+                                  "                            pred = yhat[k * 3 + c];"),
+    "blend_border_clamped": ("                    if (nx < 0 || ny < 0 || nx >= W || ny >= H) continue;\n                    size_t k",
+                             "                    nx = nx < 0 ? 0 : (nx >= W ? W - 1 : nx);\n"
+                             "                    ny = ny < 0 ? 0 : (ny >= H ? H - 1 : ny);\n                    size_t k"),
+    "blend_centre_excluded": ("                    size_t k = (size_t)ny * W + nx;\n                    double ds2",
+                              "                    if (dx == 0 && dy == 0) continue;\n"
+                              "                    size_t k = (size_t)ny * W + nx;\n                    double ds2"),
+    "blend_nonfinite_feature_kept": ("p[i] = isfinite(v) ? v : 0.0;", "p[i] = v;"),
 }
 
 
@@ -68,6 +84,7 @@ def test_pins_catch_planted_mistake(name, tmp_path):
     env = dict(os.environ, WRLS_ORACLE_LIB_OVERRIDE=str(lib), OMP_NUM_THREADS="2")
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_pins.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_paper_pins.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_paper_pins.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_blend_pins.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=300)
     assert r.returncode != 0, "planted mistake %r passed every pin:\n%s" % (name, r.stdout[-2000:])
