@@ -42,6 +42,16 @@ def algorithmic_bytes_per_pixel_paper(in_bytes: int, motion: bool = True) -> int
     return 3 * in_bytes + (8 if motion else 0) + 4 * S + 4 * S + 12
 
 
+def blend_bytes_per_pixel(d: int, in_bytes: int, paper: bool = False) -> int:
+    """The 5x5 spatial blend after a step: the current beta (3d floats) and
+    the centre's predictor source (d-1 features in the input type, or the
+    3 FP32 history planes in paper mode) read once, the step's output read
+    once as the range guide, the blended FP32 output written.  Halo re-reads
+    of neighbouring tiles are cache hits and are not counted."""
+    pred = 12 if paper else (d - 1) * in_bytes
+    return 3 * d * 4 + pred + 12 + 12
+
+
 def kernel_source_hash() -> str:
     src = os.path.join(ROOT, "paper_2106_08034_amd", "csrc", "wrls_kernels.hip")
     return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
@@ -235,6 +245,9 @@ def main():
     ap.add_argument("--pool", type=int, default=4,
                     help="c4: distinct frames generated per stream (cycled)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--blend-sigmas", type=float, nargs=2, default=(1.5, 0.15),
+                    metavar=("SIGMA_S", "SIGMA_R"),
+                    help="widths of the timed 5x5 spatial blend (after the step loop)")
     ap.add_argument("--cpu-frames", type=int, default=0,
                     help="frames of the oracle sample (0: all frames of the sequence)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -328,6 +341,21 @@ def main():
     elapsed = time.perf_counter() - t_start
     per_launch_ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(K)]
     total_ev_ms = ev[0].elapsed_time(ev[K])
+
+    # The spatial blend (a second kernel after the step), timed on its own
+    # over the last state: K launches, HIP events on the launch stream.
+    f_last = dev_frames[(args.warmup + K - 1) % wl.frames][1]
+    fin = torch.empty_like(out)
+    ss, sr = args.blend_sigmas
+    stream.blend(f_last, out, ss, sr, out=fin)
+    torch.cuda.synchronize()
+    evb = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
+    evb[0].record(cs)
+    for i in range(K):
+        stream.blend(f_last, out, ss, sr, out=fin)
+        evb[i + 1].record(cs)
+    torch.cuda.synchronize()
+    blend_ms = [evb[i].elapsed_time(evb[i + 1]) for i in range(K)]
     npix = wl.width * wl.height
     mpix_s = K * npix / elapsed / 1e6
     in_bytes = 2 if wl.in_dtype == "f16" else 4
@@ -395,6 +423,15 @@ def main():
                      "event_total_ms": round(total_ev_ms, 3)},
         "cpu_baseline": cpu,
     }
+    bbpp = blend_bytes_per_pixel(d_model, in_bytes, paper)
+    blend_s = float(np.mean(blend_ms)) / 1e3
+    line["spatial_blend"] = {
+        "kernel": "wrls blend_kernel<%d>" % d_model, "sigma_s": ss, "sigma_r": sr,
+        "avg_launch_us": round(blend_s * 1e6, 2), "mpix_per_s": round(npix / blend_s / 1e6, 1),
+        "algorithmic_bytes_per_pixel": bbpp,
+        "achieved": round(bbpp * npix / blend_s / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(bbpp * npix / blend_s / 1e9 / HBM_PEAK_GBS, 4),
+        "step_plus_blend_mpix_per_s": round(npix / (avg_launch_s + blend_s) / 1e6, 1)}
     stream.close()
     if not args.no_serving and args.workload == "c2":
         del dev_frames

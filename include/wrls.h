@@ -190,6 +190,27 @@ wrls_status wrls_get_state(const wrls_stream *s, float *P_packed, float *beta);
 wrls_status wrls_set_state(wrls_stream *s, const float *P_packed, const float *beta,
                            int64_t frames);
 
+/* Spatial blend of neighbour-model predictions (Sec. 5.3, last paragraph),
+ * run after wrls_step on the stream's current state.  Pixel i's final colour
+ * averages, over the 5 x 5 window centred on i (pixels inside the image;
+ * the window is cut at the border), the predictions p_i beta_k^T that the
+ * neighbours' models make for pixel i, with the bilateral weight
+ *   w_ik = exp(-|x_k - x_i|^2 / (2 sigma_s^2)) exp(-|yhat_k - yhat_i|^2 / (2 sigma_r^2)),
+ * |.| Euclidean (pixels; RGB), yhat = the step's output.
+ *   features  the features given to the last wrls_step ([d-1][H][W] in_dtype,
+ *             device); NULL for d = 1 and in WRLS_W_PAPER mode, where
+ *             p = [1, z] with the stored history.  Non-finite entries count
+ *             as 0, as in the step.
+ *   temporal  the output of the last wrls_step ([3][H][W] FP32, device)
+ *   sigma_s   spatial width in pixels, sigma_r range width in colour units:
+ *             > 0 with 1/(2 sigma^2) finite in binary32; +inf turns the
+ *             factor off
+ *   out       [3][H][W] FP32, device; must not alias temporal
+ * Stream-ordered on the stream's HIP stream; does not change the state.
+ * WRLS_EINVAL before the first step or on bad arguments. */
+wrls_status wrls_blend(const wrls_stream *s, const void *features, const float *temporal,
+                       float sigma_s, float sigma_r, float *out);
+
 /* WRLS_W_PAPER streams: copies the temporal feature history z out / in
  * ([3][H][W] floats, device pointers, stream-ordered).  WRLS_EINVAL for
  * other streams. */

@@ -322,6 +322,41 @@ wrls_status wrls_step(wrls_stream *s, const void *color, const void *features,
     return WRLS_OK;
 }
 
+wrls_status wrls_blend(const wrls_stream *s, const void *features, const float *temporal,
+                       float sigma_s, float sigma_r, float *out)
+{
+    if (!s) return fail(WRLS_EINVAL, "stream handle is NULL");
+    const wrls_params &p = s->prm;
+    const bool paper = p.weight_mode == WRLS_W_PAPER;
+    if (s->frames <= 0) return fail(WRLS_EINVAL, "no state yet: step a frame before blending");
+    if (!temporal || !out) return fail(WRLS_EINVAL, "temporal and out are required");
+    if (out == temporal) return fail(WRLS_EINVAL, "out must not alias temporal (its halo is read)");
+    if (p.d > 1 && !paper && !features)
+        return fail(WRLS_EINVAL, "features is NULL with d = %d", p.d);
+    // +inf turns a factor off (1/(2 sigma^2) = 0); 1/(2 sigma^2) must be
+    // finite so that a zero distance never meets an infinite factor
+    const float ss = 1.0f / (2.0f * sigma_s * sigma_s), sr = 1.0f / (2.0f * sigma_r * sigma_r);
+    if (!(sigma_s > 0.0f) || !std::isfinite(ss))
+        return fail(WRLS_EINVAL, "sigma_s = %g: must be > 0 with 1/(2 sigma_s^2) finite", (double)sigma_s);
+    if (!(sigma_r > 0.0f) || !std::isfinite(sr))
+        return fail(WRLS_EINVAL, "sigma_r = %g: must be > 0 with 1/(2 sigma_r^2) finite", (double)sigma_r);
+    wrls::BlendArgs a;
+    a.state = s->state[s->cur];
+    a.feats = paper ? nullptr : features;
+    a.guide = temporal;
+    a.out = out;
+    a.W = p.width;
+    a.H = p.height;
+    a.pitch = s->pitch;
+    a.inv2ss = ss;
+    a.inv2sr = sr;
+    a.tiles_x = (p.width + wrls::kBlendTW - 1) / wrls::kBlendTW;
+    a.tiles_y = (p.height + wrls::kBlendTH - 1) / wrls::kBlendTH;
+    hipError_t e = wrls::launch_blend(p.d, p.in_dtype == WRLS_F16, paper, a, s->st);
+    if (e != hipSuccess) return hip_fail(e, "blend launch");
+    return WRLS_OK;
+}
+
 wrls_status wrls_get_state(const wrls_stream *s, float *P_packed, float *beta)
 {
     if (!s) return fail(WRLS_EINVAL, "stream handle is NULL");

@@ -64,6 +64,26 @@ struct BatchTable {
     FrameArgs frame[kMaxBatch];
 };
 
+// Everything one launch of the spatial blend needs (Sec. 5.3, last
+// paragraph): the current state, the frame's predictor source, the step's
+// output as the range guide, and the output.
+struct BlendArgs {
+    const float *state;     // current state: S planes of `pitch` floats
+    const void *feats;      // [d-1][H][W] float or _Float16 (null in paper mode or d = 1)
+    const float *guide;     // [3][H][W] output of the step (temporal prediction)
+    float *out;             // [3][H][W]
+    int32_t W, H;
+    int64_t pitch;
+    float inv2ss, inv2sr;   // 1/(2 sigma_s^2), 1/(2 sigma_r^2); 0 turns a factor off
+    int32_t tiles_x;        // blend tiles per image row
+    int32_t tiles_y;
+};
+// Blend tile: kBlendTW x kBlendTH output pixels per workgroup of
+// kBlendTW * kBlendTH threads, window radius kBlendR.
+constexpr int kBlendTW = 64;
+constexpr int kBlendTH = 4;
+constexpr int kBlendR = 2;
+
 // S: state entries per pixel (state_floats(d), plus 3 history entries in
 // paper mode).
 hipError_t launch_reset(float *state, int64_t pitch, int64_t npix, int d, int S, float p0,
@@ -71,6 +91,9 @@ hipError_t launch_reset(float *state, int64_t pitch, int64_t npix, int d, int S,
 hipError_t launch_step(int d, bool f16, const FrameArgs &a, TileShape ts, hipStream_t st);
 // The paper's own predictor and weight (d = 4, state with history).
 hipError_t launch_step_paper(bool f16, const FrameArgs &a, TileShape ts, hipStream_t st);
+// The 5x5 spatial blend of neighbour-model predictions; paper: p = [1, z]
+// from the state's history planes (d = 4).
+hipError_t launch_blend(int d, bool f16, bool paper, const BlendArgs &a, hipStream_t st);
 // One persistent launch of `grid` workgroups of tab->tile.block_threads
 // threads over every tile of every frame in the device table `tab`.
 hipError_t launch_step_batched(int d, bool f16, const BatchTable *tab, int32_t grid,

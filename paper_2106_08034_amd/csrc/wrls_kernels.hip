@@ -503,6 +503,189 @@ hipError_t occupancy_batched_d(bool f16, int32_t block_threads, int *blocks_per_
         blocks_per_cu, reinterpret_cast<const void *>(&batch_kernel<D, float>), block_threads, 0);
 }
 
+// Spatial blend of neighbour-model predictions (Sec. 5.3, last paragraph),
+// after a step, over the current state.  Pixel i's final colour averages the
+// predictions p_i beta_k^T of the models k in the 5x5 window centred on i
+// (pixels inside the image) with the bilateral weight
+//   w_ik = exp(-|x_k - x_i|^2 / (2 sigma_s^2) - |yhat_k - yhat_i|^2 / (2 sigma_r^2)),
+// yhat being the step's output.  Since every prediction uses p_i, the sum is
+// p_i (sum_k w_ik beta_k^T) / sum_k w_ik: per channel a weighted 5x5 stencil
+// over the D beta planes, then one dot product.
+//
+// One workgroup per 64 x 4 tile.  The guide of the tile and its 2-pixel halo
+// (68 x 8) is staged in LDS and every thread keeps its 25 weights in
+// registers; then, one channel at a time, the channel's D beta planes of
+// the halo are staged in LDS (a wave reads 64 consecutive words per access:
+// no bank conflicts) and accumulated.  Halo reads of neighbouring tiles hit
+// L2; each state entry crosses HBM about once.
+constexpr int kBlendRW = kBlendTW + 2 * kBlendR;
+constexpr int kBlendRH = kBlendTH + 2 * kBlendR;
+constexpr int kBlendRN = kBlendRW * kBlendRH;
+constexpr int kBlendThreads = kBlendTW * kBlendTH;
+constexpr int kBlendSlots = (kBlendRN + kBlendThreads - 1) / kBlendThreads;
+
+// The occupancy hint caps registers: left alone, the scheduler keeps most of
+// a channel's 25 x D LDS reads in flight (168 VGPRs at d = 8, 3 waves/SIMD);
+// capped it needs 74-96 VGPRs without spills (5 waves; d = 10 needs 4).
+template <int D, typename InT, bool PAPER>
+__global__ void __launch_bounds__(kBlendThreads) __attribute__((amdgpu_waves_per_eu(D <= 9 ? 5 : 4)))
+blend_kernel(const BlendArgs a)
+{
+    constexpr int NP = packed_floats(D);
+    constexpr int NS = state_floats(D) + (PAPER ? 3 : 0);
+    __shared__ float s_guide[3][kBlendRN];
+    __shared__ float s_beta[D][kBlendRN];
+
+    const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    const int tyi = tile / a.tiles_x;
+    const int x0 = (tile - tyi * a.tiles_x) * kBlendTW, y0 = tyi * kBlendTH;
+    const int tid = (int)threadIdx.x;
+    const int lx = tid % kBlendTW, ly = tid / kBlendTW;
+    const int x = x0 + lx, y = y0 + ly;
+    const bool mine = x < a.W && y < a.H;  // no early exit: every thread stages the halo
+    const uint32_t n = (uint32_t)a.W * (uint32_t)a.H;
+    const uint32_t pbytes = (uint32_t)a.pitch * 4u;
+    const Rsrc r_state = array_rsrc(a.state, (uint32_t)NS * pbytes);
+    const Rsrc r_guide = array_rsrc(a.guide, 3u * n * 4u);
+
+    // Halo slots of this thread: global pixel index, or -1 outside the image.
+    int hj[kBlendSlots];
+#pragma unroll
+    for (int r = 0; r < kBlendSlots; r++) {
+        const int sl = tid + r * kBlendThreads;
+        const int hy = sl / kBlendRW, hx = sl - hy * kBlendRW;
+        const int gx = x0 - kBlendR + hx, gy = y0 - kBlendR + hy;
+        const bool in = sl < kBlendRN && gx >= 0 && gx < a.W && gy >= 0 && gy < a.H;
+        hj[r] = in ? gy * a.W + gx : -1;
+    }
+
+    // The centre's predictor p_i (non-finite entries as 0, as in the step).
+    const uint32_t j = mine ? (uint32_t)y * (uint32_t)a.W + (uint32_t)x : 0u;
+    float p[D];
+    p[0] = 1.0f;
+    if (PAPER) {
+#pragma unroll
+        for (int m = 1; m < D; m++)
+            p[m] = bload(r_state, j * 4u, (uint32_t)(state_floats(D) + m - 1) * pbytes);
+    } else {
+        const InT *tag = nullptr;
+        const Rsrc r_feats = array_rsrc(a.feats, (uint32_t)(D - 1) * n * (uint32_t)sizeof(InT));
+#pragma unroll
+        for (int m = 1; m < D; m++) p[m] = load_in(r_feats, tag, n, m - 1, j);
+    }
+#pragma unroll
+    for (int m = 1; m < D; m++) p[m] = finite(p[m]) ? p[m] : 0.0f;
+
+    {
+        float g[kBlendSlots][3];
+#pragma unroll
+        for (int r = 0; r < kBlendSlots; r++)
+#pragma unroll
+            for (int c = 0; c < 3; c++)
+                g[r][c] = hj[r] >= 0 ? bload(r_guide, (uint32_t)hj[r] * 4u, (uint32_t)c * n * 4u) : 0.0f;
+#pragma unroll
+        for (int r = 0; r < kBlendSlots; r++) {
+            const int sl = tid + r * kBlendThreads;
+            if (sl < kBlendRN)
+#pragma unroll
+                for (int c = 0; c < 3; c++) s_guide[c][sl] = g[r][c];
+        }
+    }
+    __syncthreads();
+
+    const int ctr = (ly + kBlendR) * kBlendRW + (lx + kBlendR);
+    float g0[3];
+#pragma unroll
+    for (int c = 0; c < 3; c++) g0[c] = s_guide[c][ctr];
+    constexpr int KW = 2 * kBlendR + 1;
+    float w[KW * KW];
+    float den = 0.0f;
+#pragma unroll
+    for (int dy = -kBlendR; dy <= kBlendR; dy++)
+#pragma unroll
+        for (int dx = -kBlendR; dx <= kBlendR; dx++) {
+            const int idx = (dy + kBlendR) * KW + (dx + kBlendR);
+            float wk = 1.0f;  // the centre
+            if (dx != 0 || dy != 0) {
+                const int k = ctr + dy * kBlendRW + dx;
+                float dr2 = 0.0f;
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    const float e = s_guide[c][k] - g0[c];
+                    dr2 = fmaf(e, e, dr2);
+                }
+                const float ex = fmaf(dr2, a.inv2sr, (float)(dx * dx + dy * dy) * a.inv2ss);
+                const bool in = x + dx >= 0 && x + dx < a.W && y + dy >= 0 && y + dy < a.H;
+                wk = in ? __expf(-ex) : 0.0f;
+            }
+            w[idx] = wk;
+            den += wk;
+        }
+
+    float outc[3];
+    // kept rolled: unrolled, the compiler hoists every channel's loads and
+    // LDS reads and runs out of registers
+#pragma unroll 1
+    for (int c = 0; c < 3; c++) {
+        if (c > 0) __syncthreads();  // the previous channel's reads are done
+        float v[kBlendSlots][D];
+#pragma unroll
+        for (int r = 0; r < kBlendSlots; r++)
+#pragma unroll
+            for (int m = 0; m < D; m++)
+                v[r][m] = hj[r] >= 0 ? bload(r_state, (uint32_t)hj[r] * 4u,
+                                             (uint32_t)(NP + c * D + m) * pbytes)
+                                     : 0.0f;
+#pragma unroll
+        for (int r = 0; r < kBlendSlots; r++) {
+            const int sl = tid + r * kBlendThreads;
+            if (sl < kBlendRN)
+#pragma unroll
+                for (int m = 0; m < D; m++) s_beta[m][sl] = v[r][m];
+        }
+        __syncthreads();
+        float acc[D];
+#pragma unroll
+        for (int m = 0; m < D; m++) acc[m] = 0.0f;
+#pragma unroll
+        for (int dy = -kBlendR; dy <= kBlendR; dy++)
+#pragma unroll
+            for (int dx = -kBlendR; dx <= kBlendR; dx++) {
+                const int idx = (dy + kBlendR) * KW + (dx + kBlendR);
+                const int k = ctr + dy * kBlendRW + dx;
+#pragma unroll
+                for (int m = 0; m < D; m++) acc[m] = fmaf(w[idx], s_beta[m][k], acc[m]);
+            }
+        float yv = 0.0f;
+#pragma unroll
+        for (int m = 0; m < D; m++) yv = fmaf(p[m], acc[m], yv);
+        outc[c] = yv / den;
+    }
+    if (mine) {
+        const Rsrc r_out = array_rsrc(a.out, 3u * n * 4u);
+#pragma unroll
+        for (int c = 0; c < 3; c++) bstore(r_out, j * 4u, (uint32_t)c * n * 4u, outc[c]);
+    }
+}
+
+template <int D>
+hipError_t launch_blend_d(bool f16, bool paper, const BlendArgs &a, hipStream_t st)
+{
+    const dim3 grid((unsigned)(a.tiles_x * a.tiles_y)), block((unsigned)kBlendThreads);
+    (void)hipGetLastError();  // report this launch's error, not an older one
+    if constexpr (D == 4) {
+        if (paper) {
+            hipLaunchKernelGGL((blend_kernel<4, float, true>), grid, block, 0, st, a);
+            return hipGetLastError();
+        }
+    }
+    if (f16)
+        hipLaunchKernelGGL((blend_kernel<D, _Float16, false>), grid, block, 0, st, a);
+    else
+        hipLaunchKernelGGL((blend_kernel<D, float, false>), grid, block, 0, st, a);
+    return hipGetLastError();
+}
+
 template <int D>
 hipError_t launch_batched_d(bool f16, const BatchTable *tab, int32_t grid, int32_t block_threads,
                             hipStream_t st)
@@ -607,6 +790,24 @@ const void *batched_kernel_fn(int d, bool f16)
     default: return nullptr;
     }
 #undef WRLS_BATCH_FN
+}
+
+hipError_t launch_blend(int d, bool f16, bool paper, const BlendArgs &a, hipStream_t st)
+{
+    if (paper && d != 4) return hipErrorInvalidValue;
+    switch (d) {
+    case 1: return launch_blend_d<1>(f16, false, a, st);
+    case 2: return launch_blend_d<2>(f16, false, a, st);
+    case 3: return launch_blend_d<3>(f16, false, a, st);
+    case 4: return launch_blend_d<4>(f16, paper, a, st);
+    case 5: return launch_blend_d<5>(f16, false, a, st);
+    case 6: return launch_blend_d<6>(f16, false, a, st);
+    case 7: return launch_blend_d<7>(f16, false, a, st);
+    case 8: return launch_blend_d<8>(f16, false, a, st);
+    case 9: return launch_blend_d<9>(f16, false, a, st);
+    case 10: return launch_blend_d<10>(f16, false, a, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t batched_blocks_per_cu(int d, bool f16, int32_t block_threads, int *blocks_per_cu)

@@ -68,6 +68,7 @@ SIGNATURES = {
     "wrls_step": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP]),
     "wrls_get_state": (ctypes.c_int, [_VP, _VP, _VP]),
     "wrls_set_state": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int64]),
+    "wrls_blend": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_float, ctypes.c_float, _VP]),
     "wrls_get_history": (ctypes.c_int, [_VP, _VP]),
     "wrls_set_history": (ctypes.c_int, [_VP, _VP]),
     "wrls_batch_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _VP,
@@ -229,6 +230,11 @@ def wrls_batch_step(b: int, handles, frames):
     _check(lib().wrls_batch_step(b, n, hs, fs))
 
 
+def wrls_blend(h: int, features, temporal, sigma_s: float, sigma_r: float, out):
+    _check(lib().wrls_blend(h, _ptr(features), _ptr(temporal), float(sigma_s), float(sigma_r),
+                            _ptr(out)))
+
+
 def wrls_get_history(h: int, z):
     _check(lib().wrls_get_history(h, _ptr(z)))
 
@@ -349,6 +355,22 @@ class Stream:
         B = torch.empty((3, d, H, W), dtype=torch.float32, device="cuda")
         wrls_get_state(self.handle, P, B)
         return P, B
+
+    def blend(self, features, temporal, sigma_s: float, sigma_r: float, out=None):
+        """The 5x5 spatial blend (wrls_blend) on the current state: features
+        of the last step (ignored in paper mode), temporal = that step's
+        output.  Returns the blended (3, H, W) image."""
+        torch = self._torch
+        W, H, d = self.W, self.H, self.d
+        use_f = d > 1 and not self.paper
+        if use_f:
+            self._chk(features, (d - 1, H, W), self.in_dtype, "features")
+        self._chk(temporal, (3, H, W), torch.float32, "temporal")
+        if out is None:
+            out = torch.empty((3, H, W), dtype=torch.float32, device=temporal.device)
+        self._chk(out, (3, H, W), torch.float32, "out")
+        wrls_blend(self.handle, features if use_f else None, temporal, sigma_s, sigma_r, out)
+        return out
 
     def get_history(self):
         """Paper mode: the temporal feature history z, (3, H, W)."""
