@@ -82,6 +82,83 @@ def make_workload(name: str):
     raise SystemExit("unknown workload %r" % name)
 
 
+def ablation_modes(d_features: int):
+    """The ablation of Sec. 5.3's choices, as (name, Stream keyword arguments).
+
+    Plain RLS (w = 1, Eq. 10) against weighted RLS, with the supplied
+    features and with the paper's temporal feature (Eq. 12).  The prior
+    P0 = I/delta acts like delta samples of unit weight (scaling every w by c
+    equals scaling delta by 1/c), so delta is given in each mode's weight
+    units: one unit-weight sample for w = 1 and for the Eq. 13 weight (at
+    most 1), one median-weight sample (1 / median variance) for inverse
+    variance weights.  A very large h makes the Eq. 13 weight 1 everywhere."""
+    import math
+    import synth
+    return [
+        ("rls_features", dict(d=d_features, weight_mode="one", delta=1.0)),
+        ("wrls_features", dict(d=d_features, weight_mode="invvar", delta=math.exp(-synth.VAR_MU))),
+        ("rls_temporal_feature", dict(d=4, weight_mode="paper", h=1e3)),
+        ("wrls_temporal_feature", dict(d=4, weight_mode="paper")),
+    ]
+
+
+def run_ablation(width: int, height: int, frames: int, warm: int, sigma_s: float = 1.5,
+                 sigma_r: float = 0.15, sweep=(0.05, 0.15, 0.5, float("inf"))):
+    """PSNR (peak 1, linear) against the clean frames, over frames warm..end,
+    of the temporal output and of the spatially blended output of every
+    ablation mode, on the c2 scene (sub-pixel pan, disocclusions,
+    heteroscedastic 1-spp noise) at the given size; also the temporal
+    flicker, the RMS frame-to-frame change of the error.  Everything runs
+    through libwrls on the GPU."""
+    import math
+    import torch
+    import synth
+    from paper_2106_08034_amd import wrls
+    wl = synth.c2(width=width, height=height, frames=frames)
+    src = synth.FrameSource(wl)
+    dev = torch.device("cuda:0")
+    up = lambda a: torch.from_numpy(a).to(dev)
+    seq = []
+    for _ in range(frames):
+        f = src.next()
+        seq.append(tuple(up(a) for a in (f.color, f.feats, f.var, f.motion, f.clean)))
+
+    def psnr(mse):
+        return round(10.0 * math.log10(1.0 / mse), 3)
+
+    res = {"input": {"psnr_db": psnr(float(sum(((c - cl) ** 2).mean().item()
+                                                   for c, _, _, _, cl in seq[warm:]) / (frames - warm)))}}
+    for name, kw in ablation_modes(wl.d):
+        d = kw.pop("d")
+        st = wrls.Stream(width, height, d, **kw)
+        paper = kw["weight_mode"] == "paper"
+        sigmas = [(sigma_s, sigma_r)] + ([(sigma_s, r) for r in sweep] if name == "wrls_features" else [])
+        se_t, se_b = 0.0, [0.0] * len(sigmas)
+        fl_t, fl_b, prev_t, prev_b = 0.0, 0.0, None, None
+        for t, (c, fe, v, m, cl) in enumerate(seq):
+            out = st.step(c, None if paper else fe, v if kw["weight_mode"] == "invvar" else None, m)
+            blends = [st.blend(None if paper else fe, out, a, b) for a, b in sigmas]
+            if t >= warm:
+                e_t, e_b = out - cl, blends[0] - cl
+                se_t += (e_t ** 2).mean().item()
+                for i, bl in enumerate(blends):
+                    se_b[i] += ((bl - cl) ** 2).mean().item()
+                if prev_t is not None:
+                    fl_t += ((e_t - prev_t) ** 2).mean().sqrt().item()
+                    fl_b += ((e_b - prev_b) ** 2).mean().sqrt().item()
+                prev_t, prev_b = e_t, e_b
+        n = frames - warm
+        rec = {"psnr_db": psnr(se_t / n), "psnr_blend_db": psnr(se_b[0] / n),
+               "flicker": round(fl_t / (n - 1), 5), "flicker_blend": round(fl_b / (n - 1), 5),
+               "stream": dict(kw, d=d)}
+        if len(sigmas) > 1:
+            rec["blend_sigma_r_sweep_db"] = {str(b): psnr(se_b[i] / n) for i, (_, b) in
+                                             enumerate(sigmas) if i > 0}
+        res[name] = rec
+        st.close()
+    return res
+
+
 def bench_serving(args):
     """32 sessions (Poisson 4/s arrivals, Exp(20 s) durations, 720p..4K,
     30..60 Hz, FP16, d = 8) served in real time for args.serve_seconds:
@@ -233,9 +310,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=60)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c2p", "c3", "c4", "c5"],
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c2p", "c3", "c4", "c5", "ablation"],
                     help="c2p: the c2 scene with the paper's own predictor and weight "
-                         "(Eq. 12-13, d = 4)")
+                         "(Eq. 12-13, d = 4); ablation: PSNR of RLS vs weighted RLS, "
+                         "supplied vs temporal feature, with and without the blend")
     ap.add_argument("--serve-seconds", type=float, default=15.0,
                     help="c5 (and the default run's serving leg): wall seconds of serving")
     ap.add_argument("--budget-gb", type=float, default=0.0,
@@ -286,6 +364,21 @@ def main():
 
     if args.workload == "c4":
         print(json.dumps(bench_batched(args)), flush=True)
+        return
+    if args.workload == "ablation":
+        W, H, T, warm = 640, 360, 60, 10
+        t0 = time.perf_counter()
+        res = run_ablation(W, H, T, warm)
+        best = max(v.get("psnr_blend_db", 0.0) for k, v in res.items() if k != "input")
+        line = {"metric": "PSNR dB vs clean frames (ablation of Sec. 5.3)", "value": best,
+                "unit": "dB", "n_gpus": 1, "steps": T, "warmup": warm,
+                "ms_per_step": round((time.perf_counter() - t0) * 1e3 / T, 3),
+                "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+                "data": "synthetic (seeded procedural scene with its clean frames)",
+                "config": {"workload": "c2-scene-%dx%d-%dframes-ablation" % (W, H, T),
+                           "psnr_frames": "%d..%d" % (warm, T - 1), "blend_sigmas": [1.5, 0.15]},
+                "ablation": res, "cpu_baseline": None}
+        print(json.dumps(line), flush=True)
         return
     if args.workload == "c5":
         res = bench_serving(args)

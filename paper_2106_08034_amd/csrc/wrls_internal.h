@@ -79,9 +79,11 @@ struct BlendArgs {
     int32_t tiles_y;
 };
 // Blend tile: kBlendTW x kBlendTH output pixels per workgroup of
-// kBlendTW * kBlendTH threads, window radius kBlendR.
+// kBlendTW * kBlendTH / kBlendRPT threads (each thread computes kBlendRPT
+// vertically adjacent pixels), window radius kBlendR.
 constexpr int kBlendTW = 64;
-constexpr int kBlendTH = 4;
+constexpr int kBlendRPT = 2;
+constexpr int kBlendTH = 4 * kBlendRPT;
 constexpr int kBlendR = 2;
 
 // S: state entries per pixel (state_floats(d), plus 3 history entries in

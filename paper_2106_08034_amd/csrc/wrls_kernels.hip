@@ -512,25 +512,29 @@ hipError_t occupancy_batched_d(bool f16, int32_t block_threads, int *blocks_per_
 // p_i (sum_k w_ik beta_k^T) / sum_k w_ik: per channel a weighted 5x5 stencil
 // over the D beta planes, then one dot product.
 //
-// One workgroup per 64 x 4 tile.  The guide of the tile and its 2-pixel halo
-// (68 x 8) is staged in LDS and every thread keeps its 25 weights in
-// registers; then, one channel at a time, the channel's D beta planes of
-// the halo are staged in LDS (a wave reads 64 consecutive words per access:
-// no bank conflicts) and accumulated.  Halo reads of neighbouring tiles hit
-// L2; each state entry crosses HBM about once.
+// One workgroup per 64 x kBlendTH tile; each thread computes RPT vertically
+// adjacent pixels.  The guide of the tile and its 2-pixel halo is staged in
+// LDS and every thread keeps its 25 RPT weights in registers; then, one
+// channel at a time, the channel's D beta planes of the halo are staged in
+// LDS and accumulated.  A wave covers 64 consecutive columns, so its LDS
+// reads are 64 consecutive words (no bank conflicts); a thread reads each
+// halo row once for all RPT of its pixels, so LDS traffic per pixel falls
+// from 25 to 5 (RPT + 4) / RPT reads per entry.  Halo reads of neighbouring
+// tiles hit L2; each state entry crosses HBM about once.
 constexpr int kBlendRW = kBlendTW + 2 * kBlendR;
 constexpr int kBlendRH = kBlendTH + 2 * kBlendR;
 constexpr int kBlendRN = kBlendRW * kBlendRH;
-constexpr int kBlendThreads = kBlendTW * kBlendTH;
+constexpr int kBlendThreads = kBlendTW * kBlendTH / kBlendRPT;
 constexpr int kBlendSlots = (kBlendRN + kBlendThreads - 1) / kBlendThreads;
+constexpr int kBlendK = 2 * kBlendR + 1;  // window side
 
 // The occupancy hint caps registers: left alone, the scheduler keeps most of
-// a channel's 25 x D LDS reads in flight (168 VGPRs at d = 8, 3 waves/SIMD);
-// capped it needs 74-96 VGPRs without spills (5 waves; d = 10 needs 4).
+// a channel's LDS reads in flight and needs 168+ VGPRs at d = 8.
 template <int D, typename InT, bool PAPER>
-__global__ void __launch_bounds__(kBlendThreads) __attribute__((amdgpu_waves_per_eu(D <= 9 ? 5 : 4)))
+__global__ void __launch_bounds__(kBlendThreads) __attribute__((amdgpu_waves_per_eu(D <= 7 ? 4 : (D <= 9 ? 3 : 2))))
 blend_kernel(const BlendArgs a)
 {
+    constexpr int RPT = kBlendRPT;
     constexpr int NP = packed_floats(D);
     constexpr int NS = state_floats(D) + (PAPER ? 3 : 0);
     __shared__ float s_guide[3][kBlendRN];
@@ -540,9 +544,8 @@ blend_kernel(const BlendArgs a)
     const int tyi = tile / a.tiles_x;
     const int x0 = (tile - tyi * a.tiles_x) * kBlendTW, y0 = tyi * kBlendTH;
     const int tid = (int)threadIdx.x;
-    const int lx = tid % kBlendTW, ly = tid / kBlendTW;
-    const int x = x0 + lx, y = y0 + ly;
-    const bool mine = x < a.W && y < a.H;  // no early exit: every thread stages the halo
+    const int lx = tid % kBlendTW, ly = (tid / kBlendTW) * RPT;  // first of the thread's rows
+    const int x = x0 + lx;
     const uint32_t n = (uint32_t)a.W * (uint32_t)a.H;
     const uint32_t pbytes = (uint32_t)a.pitch * 4u;
     const Rsrc r_state = array_rsrc(a.state, (uint32_t)NS * pbytes);
@@ -559,22 +562,28 @@ blend_kernel(const BlendArgs a)
         hj[r] = in ? gy * a.W + gx : -1;
     }
 
-    // The centre's predictor p_i (non-finite entries as 0, as in the step).
-    const uint32_t j = mine ? (uint32_t)y * (uint32_t)a.W + (uint32_t)x : 0u;
-    float p[D];
-    p[0] = 1.0f;
-    if (PAPER) {
+    // No early exit for pixels outside the image: every thread stages the halo.
+    bool mine[RPT];
+    uint32_t jr[RPT];
 #pragma unroll
-        for (int m = 1; m < D; m++)
-            p[m] = bload(r_state, j * 4u, (uint32_t)(state_floats(D) + m - 1) * pbytes);
-    } else {
-        const InT *tag = nullptr;
-        const Rsrc r_feats = array_rsrc(a.feats, (uint32_t)(D - 1) * n * (uint32_t)sizeof(InT));
-#pragma unroll
-        for (int m = 1; m < D; m++) p[m] = load_in(r_feats, tag, n, m - 1, j);
+    for (int r = 0; r < RPT; r++) {
+        const int y = y0 + ly + r;
+        mine[r] = x < a.W && y < a.H;
+        jr[r] = mine[r] ? (uint32_t)y * (uint32_t)a.W + (uint32_t)x : 0u;
     }
-#pragma unroll
-    for (int m = 1; m < D; m++) p[m] = finite(p[m]) ? p[m] : 0.0f;
+    // Predictor entry m >= 1 of pixel jj (non-finite as 0, as in the step);
+    // re-read per channel (cache hits) rather than held in registers.
+    const Rsrc r_feats = array_rsrc(a.feats, (uint32_t)(D - 1) * n * (uint32_t)sizeof(InT));
+    auto pred_entry = [&](uint32_t jj, int m) {
+        float v;
+        if (PAPER) {
+            v = bload(r_state, jj * 4u, (uint32_t)(state_floats(D) + m - 1) * pbytes);
+        } else {
+            const InT *tag = nullptr;
+            v = load_in(r_feats, tag, n, m - 1, jj);
+        }
+        return finite(v) ? v : 0.0f;
+    };
 
     {
         float g[kBlendSlots][3];
@@ -593,79 +602,127 @@ blend_kernel(const BlendArgs a)
     }
     __syncthreads();
 
-    const int ctr = (ly + kBlendR) * kBlendRW + (lx + kBlendR);
-    float g0[3];
+    // Weights: halo row hr (0 .. RPT+3 relative to the thread's first row
+    // minus the radius) serves output r at row offset dy = hr - r - R.  The
+    // exponent is evaluated in base 2 (exp(-e) = 2^(-e log2 e)); the spatial
+    // part takes one of the five distinct squared distances 1, 2, 4, 5, 8.
+    // A tile whose windows all lie inside the image (uniform over the
+    // workgroup) skips the per-neighbour bounds test.
+    constexpr float kLog2e = 1.4426950408889634f;
+    const float nr = -a.inv2sr * kLog2e;
+    float ns[9];
 #pragma unroll
-    for (int c = 0; c < 3; c++) g0[c] = s_guide[c][ctr];
-    constexpr int KW = 2 * kBlendR + 1;
-    float w[KW * KW];
-    float den = 0.0f;
+    for (int q = 1; q <= 8; q++) ns[q] = -(float)q * a.inv2ss * kLog2e;
+    const bool interior = x0 >= kBlendR && x0 + kBlendTW + kBlendR <= a.W && y0 >= kBlendR &&
+                          y0 + kBlendTH + kBlendR <= a.H;
+    float g0[RPT][3];
 #pragma unroll
-    for (int dy = -kBlendR; dy <= kBlendR; dy++)
+    for (int r = 0; r < RPT; r++)
+#pragma unroll
+        for (int c = 0; c < 3; c++) g0[r][c] = s_guide[c][(ly + r + kBlendR) * kBlendRW + lx + kBlendR];
+    float w[RPT][kBlendK * kBlendK];
+    float den[RPT];
+#pragma unroll
+    for (int r = 0; r < RPT; r++) den[r] = 1.0f;  // the centre
+#pragma unroll
+    for (int hr = 0; hr < RPT + 2 * kBlendR; hr++)
 #pragma unroll
         for (int dx = -kBlendR; dx <= kBlendR; dx++) {
-            const int idx = (dy + kBlendR) * KW + (dx + kBlendR);
-            float wk = 1.0f;  // the centre
-            if (dx != 0 || dy != 0) {
-                const int k = ctr + dy * kBlendRW + dx;
+            const int k = (ly + hr) * kBlendRW + lx + kBlendR + dx;
+            float gk[3];
+#pragma unroll
+            for (int c = 0; c < 3; c++) gk[c] = s_guide[c][k];
+#pragma unroll
+            for (int r = 0; r < RPT; r++) {
+                const int dy = hr - r - kBlendR;
+                if (dy < -kBlendR || dy > kBlendR) continue;
+                const int idx = (dy + kBlendR) * kBlendK + (dx + kBlendR);
+                if (dx == 0 && dy == 0) {
+                    w[r][idx] = 1.0f;
+                    continue;
+                }
                 float dr2 = 0.0f;
 #pragma unroll
                 for (int c = 0; c < 3; c++) {
-                    const float e = s_guide[c][k] - g0[c];
+                    const float e = gk[c] - g0[r][c];
                     dr2 = fmaf(e, e, dr2);
                 }
-                const float ex = fmaf(dr2, a.inv2sr, (float)(dx * dx + dy * dy) * a.inv2ss);
-                const bool in = x + dx >= 0 && x + dx < a.W && y + dy >= 0 && y + dy < a.H;
-                wk = in ? __expf(-ex) : 0.0f;
+                float wk = __builtin_amdgcn_exp2f(fmaf(dr2, nr, ns[dx * dx + dy * dy]));
+                if (!interior) {
+                    const int yy = y0 + ly + r + dy;
+                    const bool in = x + dx >= 0 && x + dx < a.W && yy >= 0 && yy < a.H;
+                    wk = in ? wk : 0.0f;
+                }
+                w[r][idx] = wk;
+                den[r] += wk;
             }
-            w[idx] = wk;
-            den += wk;
         }
 
-    float outc[3];
+    float outc[RPT][3];
     // kept rolled: unrolled, the compiler hoists every channel's loads and
     // LDS reads and runs out of registers
 #pragma unroll 1
     for (int c = 0; c < 3; c++) {
         if (c > 0) __syncthreads();  // the previous channel's reads are done
-        float v[kBlendSlots][D];
+        // staged two slots at a time: the barrier keeps the compiler from
+        // hoisting every slot's loads (and their registers) together
 #pragma unroll
-        for (int r = 0; r < kBlendSlots; r++)
+        for (int r0 = 0; r0 < kBlendSlots; r0 += 2) {
+            float v[2][D];
 #pragma unroll
-            for (int m = 0; m < D; m++)
-                v[r][m] = hj[r] >= 0 ? bload(r_state, (uint32_t)hj[r] * 4u,
-                                             (uint32_t)(NP + c * D + m) * pbytes)
-                                     : 0.0f;
+            for (int q = 0; q < 2; q++)
 #pragma unroll
-        for (int r = 0; r < kBlendSlots; r++) {
-            const int sl = tid + r * kBlendThreads;
-            if (sl < kBlendRN)
+                for (int m = 0; m < D; m++)
+                    v[q][m] = (r0 + q < kBlendSlots && hj[r0 + q] >= 0)
+                                  ? bload(r_state, (uint32_t)hj[r0 + q] * 4u,
+                                          (uint32_t)(NP + c * D + m) * pbytes)
+                                  : 0.0f;
 #pragma unroll
-                for (int m = 0; m < D; m++) s_beta[m][sl] = v[r][m];
+            for (int q = 0; q < 2; q++) {
+                const int sl = tid + (r0 + q) * kBlendThreads;
+                if (r0 + q < kBlendSlots && sl < kBlendRN)
+#pragma unroll
+                    for (int m = 0; m < D; m++) s_beta[m][sl] = v[q][m];
+            }
+            __builtin_amdgcn_sched_barrier(0);
         }
         __syncthreads();
-        float acc[D];
+        float acc[RPT][D];
 #pragma unroll
-        for (int m = 0; m < D; m++) acc[m] = 0.0f;
+        for (int r = 0; r < RPT; r++)
 #pragma unroll
-        for (int dy = -kBlendR; dy <= kBlendR; dy++)
+            for (int m = 0; m < D; m++) acc[r][m] = 0.0f;
+#pragma unroll
+        for (int hr = 0; hr < RPT + 2 * kBlendR; hr++)
 #pragma unroll
             for (int dx = -kBlendR; dx <= kBlendR; dx++) {
-                const int idx = (dy + kBlendR) * KW + (dx + kBlendR);
-                const int k = ctr + dy * kBlendRW + dx;
+                const int k = (ly + hr) * kBlendRW + lx + kBlendR + dx;
+                float b[D];
 #pragma unroll
-                for (int m = 0; m < D; m++) acc[m] = fmaf(w[idx], s_beta[m][k], acc[m]);
+                for (int m = 0; m < D; m++) b[m] = s_beta[m][k];
+#pragma unroll
+                for (int r = 0; r < RPT; r++) {
+                    const int dy = hr - r - kBlendR;
+                    if (dy < -kBlendR || dy > kBlendR) continue;
+                    const float wk = w[r][(dy + kBlendR) * kBlendK + (dx + kBlendR)];
+#pragma unroll
+                    for (int m = 0; m < D; m++) acc[r][m] = fmaf(wk, b[m], acc[r][m]);
+                }
             }
-        float yv = 0.0f;
 #pragma unroll
-        for (int m = 0; m < D; m++) yv = fmaf(p[m], acc[m], yv);
-        outc[c] = yv / den;
-    }
-    if (mine) {
-        const Rsrc r_out = array_rsrc(a.out, 3u * n * 4u);
+        for (int r = 0; r < RPT; r++) {
+            float yv = acc[r][0];  // p_0 = 1
 #pragma unroll
-        for (int c = 0; c < 3; c++) bstore(r_out, j * 4u, (uint32_t)c * n * 4u, outc[c]);
+            for (int m = 1; m < D; m++) yv = fmaf(pred_entry(jr[r], m), acc[r][m], yv);
+            outc[r][c] = yv / den[r];
+        }
     }
+    const Rsrc r_out = array_rsrc(a.out, 3u * n * 4u);
+#pragma unroll
+    for (int r = 0; r < RPT; r++)
+        if (mine[r])
+#pragma unroll
+            for (int c = 0; c < 3; c++) bstore(r_out, jr[r] * 4u, (uint32_t)c * n * 4u, outc[r][c]);
 }
 
 template <int D>
