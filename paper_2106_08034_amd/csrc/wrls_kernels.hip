@@ -515,12 +515,16 @@ hipError_t occupancy_batched_d(bool f16, int32_t block_threads, int *blocks_per_
 // One workgroup per 64 x kBlendTH tile; each thread computes RPT vertically
 // adjacent pixels.  The guide of the tile and its 2-pixel halo is staged in
 // LDS and every thread keeps its 25 RPT weights in registers; then, one
-// channel at a time, the channel's D beta planes of the halo are staged in
-// LDS and accumulated.  A wave covers 64 consecutive columns, so its LDS
-// reads are 64 consecutive words (no bank conflicts); a thread reads each
-// halo row once for all RPT of its pixels, so LDS traffic per pixel falls
-// from 25 to 5 (RPT + 4) / RPT reads per entry.  Halo reads of neighbouring
-// tiles hit L2; each state entry crosses HBM about once.
+// channel at a time, the channel's beta planes of the halo are staged in
+// LDS and accumulated.  A thread reads each halo row once for all RPT of
+// its pixels (LDS traffic per pixel: 5 (RPT + 4) / RPT reads instead of 25).
+// LDS holds the planes in groups of four, one 16-byte vector per halo pixel
+// and group (the guide likewise, padded): a neighbour costs one 128-bit read
+// per group, every read is an immediate offset from one base address (no
+// per-read address arithmetic on the vector ALU, which bounds this kernel),
+// and a wave's read covers 1 KB of consecutive bytes (no bank conflicts).
+// Halo reads of neighbouring tiles hit L2; each state entry crosses HBM
+// about once.
 constexpr int kBlendRW = kBlendTW + 2 * kBlendR;
 constexpr int kBlendRH = kBlendTH + 2 * kBlendR;
 constexpr int kBlendRN = kBlendRW * kBlendRH;
@@ -537,8 +541,9 @@ blend_kernel(const BlendArgs a)
     constexpr int RPT = kBlendRPT;
     constexpr int NP = packed_floats(D);
     constexpr int NS = state_floats(D) + (PAPER ? 3 : 0);
-    __shared__ float s_guide[3][kBlendRN];
-    __shared__ float s_beta[D][kBlendRN];
+    constexpr int NG = (D + 3) / 4;  // groups of four beta planes
+    __shared__ float4 s_guide[kBlendRN];
+    __shared__ float4 s_beta[NG][kBlendRN];
 
     const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
     const int tyi = tile / a.tiles_x;
@@ -595,9 +600,7 @@ blend_kernel(const BlendArgs a)
 #pragma unroll
         for (int r = 0; r < kBlendSlots; r++) {
             const int sl = tid + r * kBlendThreads;
-            if (sl < kBlendRN)
-#pragma unroll
-                for (int c = 0; c < 3; c++) s_guide[c][sl] = g[r][c];
+            if (sl < kBlendRN) s_guide[sl] = make_float4(g[r][0], g[r][1], g[r][2], 0.0f);
         }
     }
     __syncthreads();
@@ -615,48 +618,46 @@ blend_kernel(const BlendArgs a)
     for (int q = 1; q <= 8; q++) ns[q] = -(float)q * a.inv2ss * kLog2e;
     const bool interior = x0 >= kBlendR && x0 + kBlendTW + kBlendR <= a.W && y0 >= kBlendR &&
                           y0 + kBlendTH + kBlendR <= a.H;
-    float g0[RPT][3];
+    float4 g0[RPT];
 #pragma unroll
-    for (int r = 0; r < RPT; r++)
-#pragma unroll
-        for (int c = 0; c < 3; c++) g0[r][c] = s_guide[c][(ly + r + kBlendR) * kBlendRW + lx + kBlendR];
+    for (int r = 0; r < RPT; r++) g0[r] = s_guide[(ly + r + kBlendR) * kBlendRW + lx + kBlendR];
     float w[RPT][kBlendK * kBlendK];
     float den[RPT];
+    auto weights = [&](auto check) {
+        constexpr bool CHECK = decltype(check)::value;
 #pragma unroll
-    for (int r = 0; r < RPT; r++) den[r] = 1.0f;  // the centre
+        for (int r = 0; r < RPT; r++) den[r] = 1.0f;  // the centre
 #pragma unroll
-    for (int hr = 0; hr < RPT + 2 * kBlendR; hr++)
+        for (int hr = 0; hr < RPT + 2 * kBlendR; hr++)
 #pragma unroll
-        for (int dx = -kBlendR; dx <= kBlendR; dx++) {
-            const int k = (ly + hr) * kBlendRW + lx + kBlendR + dx;
-            float gk[3];
+            for (int dx = -kBlendR; dx <= kBlendR; dx++) {
+                const float4 gk = s_guide[(ly + hr) * kBlendRW + lx + kBlendR + dx];
 #pragma unroll
-            for (int c = 0; c < 3; c++) gk[c] = s_guide[c][k];
-#pragma unroll
-            for (int r = 0; r < RPT; r++) {
-                const int dy = hr - r - kBlendR;
-                if (dy < -kBlendR || dy > kBlendR) continue;
-                const int idx = (dy + kBlendR) * kBlendK + (dx + kBlendR);
-                if (dx == 0 && dy == 0) {
-                    w[r][idx] = 1.0f;
-                    continue;
+                for (int r = 0; r < RPT; r++) {
+                    const int dy = hr - r - kBlendR;
+                    if (dy < -kBlendR || dy > kBlendR) continue;
+                    const int idx = (dy + kBlendR) * kBlendK + (dx + kBlendR);
+                    if (dx == 0 && dy == 0) {
+                        w[r][idx] = 1.0f;
+                        continue;
+                    }
+                    const float e0 = gk.x - g0[r].x, e1 = gk.y - g0[r].y, e2 = gk.z - g0[r].z;
+                    const float dr2 = fmaf(e2, e2, fmaf(e1, e1, e0 * e0));
+                    float wk = __builtin_amdgcn_exp2f(fmaf(dr2, nr, ns[dx * dx + dy * dy]));
+                    if (CHECK) {
+                        const int yy = y0 + ly + r + dy;
+                        const bool in = x + dx >= 0 && x + dx < a.W && yy >= 0 && yy < a.H;
+                        wk = in ? wk : 0.0f;
+                    }
+                    w[r][idx] = wk;
+                    den[r] += wk;
                 }
-                float dr2 = 0.0f;
-#pragma unroll
-                for (int c = 0; c < 3; c++) {
-                    const float e = gk[c] - g0[r][c];
-                    dr2 = fmaf(e, e, dr2);
-                }
-                float wk = __builtin_amdgcn_exp2f(fmaf(dr2, nr, ns[dx * dx + dy * dy]));
-                if (!interior) {
-                    const int yy = y0 + ly + r + dy;
-                    const bool in = x + dx >= 0 && x + dx < a.W && yy >= 0 && yy < a.H;
-                    wk = in ? wk : 0.0f;
-                }
-                w[r][idx] = wk;
-                den[r] += wk;
             }
-        }
+    };
+    if (interior)
+        weights(std::false_type{});
+    else
+        weights(std::true_type{});
 
     float outc[RPT][3];
     // kept rolled: unrolled, the compiler hoists every channel's loads and
@@ -668,12 +669,12 @@ blend_kernel(const BlendArgs a)
         // hoisting every slot's loads (and their registers) together
 #pragma unroll
         for (int r0 = 0; r0 < kBlendSlots; r0 += 2) {
-            float v[2][D];
+            float v[2][4 * NG];
 #pragma unroll
             for (int q = 0; q < 2; q++)
 #pragma unroll
-                for (int m = 0; m < D; m++)
-                    v[q][m] = (r0 + q < kBlendSlots && hj[r0 + q] >= 0)
+                for (int m = 0; m < 4 * NG; m++)
+                    v[q][m] = (m < D && r0 + q < kBlendSlots && hj[r0 + q] >= 0)
                                   ? bload(r_state, (uint32_t)hj[r0 + q] * 4u,
                                           (uint32_t)(NP + c * D + m) * pbytes)
                                   : 0.0f;
@@ -682,33 +683,36 @@ blend_kernel(const BlendArgs a)
                 const int sl = tid + (r0 + q) * kBlendThreads;
                 if (r0 + q < kBlendSlots && sl < kBlendRN)
 #pragma unroll
-                    for (int m = 0; m < D; m++) s_beta[m][sl] = v[q][m];
+                    for (int gq = 0; gq < NG; gq++)
+                        s_beta[gq][sl] = make_float4(v[q][4 * gq], v[q][4 * gq + 1], v[q][4 * gq + 2],
+                                                     v[q][4 * gq + 3]);
             }
             __builtin_amdgcn_sched_barrier(0);
         }
         __syncthreads();
-        float acc[RPT][D];
+        float acc[RPT][4 * NG];
 #pragma unroll
         for (int r = 0; r < RPT; r++)
 #pragma unroll
-            for (int m = 0; m < D; m++) acc[r][m] = 0.0f;
+            for (int m = 0; m < 4 * NG; m++) acc[r][m] = 0.0f;
 #pragma unroll
-        for (int hr = 0; hr < RPT + 2 * kBlendR; hr++)
+        for (int gq = 0; gq < NG; gq++)
 #pragma unroll
-            for (int dx = -kBlendR; dx <= kBlendR; dx++) {
-                const int k = (ly + hr) * kBlendRW + lx + kBlendR + dx;
-                float b[D];
+            for (int hr = 0; hr < RPT + 2 * kBlendR; hr++)
 #pragma unroll
-                for (int m = 0; m < D; m++) b[m] = s_beta[m][k];
+                for (int dx = -kBlendR; dx <= kBlendR; dx++) {
+                    const float4 bv = s_beta[gq][(ly + hr) * kBlendRW + lx + kBlendR + dx];
+                    const float b4[4] = {bv.x, bv.y, bv.z, bv.w};
 #pragma unroll
-                for (int r = 0; r < RPT; r++) {
-                    const int dy = hr - r - kBlendR;
-                    if (dy < -kBlendR || dy > kBlendR) continue;
-                    const float wk = w[r][(dy + kBlendR) * kBlendK + (dx + kBlendR)];
+                    for (int r = 0; r < RPT; r++) {
+                        const int dy = hr - r - kBlendR;
+                        if (dy < -kBlendR || dy > kBlendR) continue;
+                        const float wk = w[r][(dy + kBlendR) * kBlendK + (dx + kBlendR)];
 #pragma unroll
-                    for (int m = 0; m < D; m++) acc[r][m] = fmaf(wk, b[m], acc[r][m]);
+                        for (int e = 0; e < 4; e++)
+                            if (4 * gq + e < D) acc[r][4 * gq + e] = fmaf(wk, b4[e], acc[r][4 * gq + e]);
+                    }
                 }
-            }
 #pragma unroll
         for (int r = 0; r < RPT; r++) {
             float yv = acc[r][0];  // p_0 = 1
