@@ -57,10 +57,12 @@ def kernel_source_hash() -> str:
     return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
 
 
-def load_traffic(workload: str):
-    """HBM traffic per launch from the committed rocprofv3 counter summary,
-    if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % workload)
+def load_traffic(workload: str, kernel: str = ""):
+    """HBM traffic per launch from the committed rocprofv3 counter summary
+    (kernel "" = the step kernel, "blend" = the spatial blend), if it was
+    taken on the current kernel source."""
+    name = "traffic_%s%s.json" % (kernel + "_" if kernel else "", workload)
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
@@ -524,6 +526,7 @@ def main():
         "algorithmic_bytes_per_pixel": bbpp,
         "achieved": round(bbpp * npix / blend_s / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(bbpp * npix / blend_s / 1e9 / HBM_PEAK_GBS, 4),
+        "traffic": load_traffic(args.workload, "blend"),
         "step_plus_blend_mpix_per_s": round(npix / (avg_launch_s + blend_s) / 1e6, 1)}
     stream.close()
     if not args.no_serving and args.workload == "c2":

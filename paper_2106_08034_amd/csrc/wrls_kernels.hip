@@ -279,8 +279,12 @@ __device__ __forceinline__ void update_pixel(const FrameArgs &a, int x, int y)
 // The per-pixel update with the paper's own predictor and weight (Sec. 5.3):
 // p = [1, z] with the temporal feature z of Eq. 12 and the weight of Eq. 13.
 // State: packed P (10), beta (12), then the history z (3).
+// col: the frame's colour over the workgroup's tile and a 1-pixel halo,
+// staged in LDS as 3 planes of nc floats (NaN outside the image), rows of
+// rw floats; c0: this pixel's position in a plane.
 template <typename InT>
-__device__ __forceinline__ void update_pixel_paper(const FrameArgs &a, int x, int y)
+__device__ __forceinline__ void update_pixel_paper(const FrameArgs &a, int x, int y,
+                                                   const float *col, int nc, int rw, int c0)
 {
     constexpr int D = 4;
     constexpr int NP = packed_floats(D);
@@ -291,9 +295,11 @@ __device__ __forceinline__ void update_pixel_paper(const FrameArgs &a, int x, in
     const InT *tag = nullptr;
     const Rsrc r_color = array_rsrc(a.color, 3u * n * (uint32_t)sizeof(InT));
 
+    (void)r_color;
+    (void)tag;
     float yc[3];
 #pragma unroll
-    for (int c = 0; c < 3; c++) yc[c] = load_in(r_color, tag, n, c, j);
+    for (int c = 0; c < 3; c++) yc[c] = col[c * nc + c0];
     const bool ok = finite(yc[0]) && finite(yc[1]) && finite(yc[2]);
 
     float st[NS];
@@ -306,22 +312,20 @@ __device__ __forceinline__ void update_pixel_paper(const FrameArgs &a, int x, in
         // current colour; without history z is the colour itself.
         float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
         if (have) {
+            // the halo holds NaN outside the image, so one finiteness test
+            // excludes both outside and non-finite neighbours
 #pragma unroll
             for (int dy = -1; dy <= 1; dy++)
 #pragma unroll
-                for (int dx = -1; dx <= 1; dx++) {
-                    const int nx = x + dx, ny = y + dy;
-                    if (nx < 0 || ny < 0 || nx >= a.W || ny >= a.H) continue;
-                    const uint32_t jn = (uint32_t)ny * (uint32_t)a.W + (uint32_t)nx;
+                for (int dx = -1; dx <= 1; dx++)
 #pragma unroll
                     for (int c = 0; c < 3; c++) {
-                        const float v = load_in(r_color, tag, n, c, jn);
+                        const float v = col[c * nc + c0 + dy * rw + dx];
                         if (finite(v)) {
                             lo[c] = fminf(lo[c], v);
                             hi[c] = fmaxf(hi[c], v);
                         }
                     }
-                }
         }
 #pragma unroll
         for (int c = 0; c < 3; c++) {
@@ -393,17 +397,35 @@ __global__ void __launch_bounds__(256) step_kernel(const FrameArgs a, const Tile
     update_pixel<D, InT>(a, x, y);
 }
 
+// The tile's colour and a 1-pixel halo are staged in LDS once per
+// workgroup (dynamic size 3 (tw + 2) (th + 2) floats): the 3x3 clamp bounds
+// then cost LDS reads instead of 27 global loads per pixel.
 template <typename InT>
 __global__ void __launch_bounds__(256) paper_step_kernel(const FrameArgs a, const TileShape ts)
 {
+    extern __shared__ float s_col[];
     const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
     int tx, ty;
     tile_coords(tile, a.tiles_x, a.tiles_y, a.strip_w, tx, ty);
-    const int tw_mask = (1 << ts.tw_log2) - 1;
-    const int x = (tx << ts.tw_log2) + ((int)threadIdx.x & tw_mask);
-    const int y = ty * (ts.block_threads >> ts.tw_log2) + ((int)threadIdx.x >> ts.tw_log2);
-    if (x >= a.W || y >= a.H) return;
-    update_pixel_paper<InT>(a, x, y);
+    const int tw = 1 << ts.tw_log2, th = ts.block_threads >> ts.tw_log2;
+    const int lx = (int)threadIdx.x & (tw - 1), ly = (int)threadIdx.x >> ts.tw_log2;
+    const int x0 = tx << ts.tw_log2, y0 = ty * th;
+    const int rw = tw + 2, nc = rw * (th + 2);
+    const uint32_t n = (uint32_t)a.W * (uint32_t)a.H;
+    const InT *tag = nullptr;
+    const Rsrc r_color = array_rsrc(a.color, 3u * n * (uint32_t)sizeof(InT));
+    for (int sl = (int)threadIdx.x; sl < nc; sl += ts.block_threads) {
+        const int hy = sl / rw, hx = sl - hy * rw;
+        const int gx = x0 - 1 + hx, gy = y0 - 1 + hy;
+        const bool in = gx >= 0 && gx < a.W && gy >= 0 && gy < a.H;
+        const uint32_t jn = in ? (uint32_t)gy * (uint32_t)a.W + (uint32_t)gx : 0u;
+#pragma unroll
+        for (int c = 0; c < 3; c++) s_col[c * nc + sl] = in ? load_in(r_color, tag, n, c, jn) : __builtin_nanf("");
+    }
+    __syncthreads();
+    const int x = x0 + lx, y = y0 + ly;
+    if (x >= a.W || y >= a.H) return;  // after the barrier
+    update_pixel_paper<InT>(a, x, y, s_col, nc, rw, (ly + 1) * rw + lx + 1);
 }
 
 // Initial state: P = p0 * I (p0 = 1 / delta), beta = 0 (and a zero history
@@ -789,10 +811,11 @@ hipError_t launch_step_paper(bool f16, const FrameArgs &a, TileShape ts, hipStre
     const int strip_w = ts.strip_w <= 0 ? tiles_x : ts.strip_w;
     b.strip_w = strip_w > tiles_x ? tiles_x : strip_w;
     const dim3 grid((unsigned)(tiles_x * tiles_y)), block((unsigned)ts.block_threads);
+    const size_t lds = 3u * (size_t)(tw + 2) * (size_t)(th + 2) * sizeof(float);
     if (f16)
-        hipLaunchKernelGGL((paper_step_kernel<_Float16>), grid, block, 0, st, b, ts);
+        hipLaunchKernelGGL((paper_step_kernel<_Float16>), grid, block, lds, st, b, ts);
     else
-        hipLaunchKernelGGL((paper_step_kernel<float>), grid, block, 0, st, b, ts);
+        hipLaunchKernelGGL((paper_step_kernel<float>), grid, block, lds, st, b, ts);
     return hipGetLastError();
 }
 
