@@ -557,7 +557,7 @@ constexpr int kBlendK = 2 * kBlendR + 1;  // window side
 // The occupancy hint caps registers: left alone, the scheduler keeps most of
 // a channel's LDS reads in flight and needs 168+ VGPRs at d = 8.
 template <int D, typename InT, bool PAPER>
-__global__ void __launch_bounds__(kBlendThreads) __attribute__((amdgpu_waves_per_eu(D <= 7 ? 4 : (D <= 9 ? 3 : 2))))
+__global__ void __launch_bounds__(kBlendThreads) __attribute__((amdgpu_waves_per_eu(D <= 4 ? 5 : (D <= 7 ? 4 : (D <= 9 ? 3 : 2)))))
 blend_kernel(const BlendArgs a)
 {
     constexpr int RPT = kBlendRPT;
@@ -598,19 +598,23 @@ blend_kernel(const BlendArgs a)
         mine[r] = x < a.W && y < a.H;
         jr[r] = mine[r] ? (uint32_t)y * (uint32_t)a.W + (uint32_t)x : 0u;
     }
-    // Predictor entry m >= 1 of pixel jj (non-finite as 0, as in the step);
-    // re-read per channel (cache hits) rather than held in registers.
+    // The pixels' predictors p_i, entries 1..D-1 (non-finite as 0, as in
+    // the step; p_0 = 1).
     const Rsrc r_feats = array_rsrc(a.feats, (uint32_t)(D - 1) * n * (uint32_t)sizeof(InT));
-    auto pred_entry = [&](uint32_t jj, int m) {
-        float v;
-        if (PAPER) {
-            v = bload(r_state, jj * 4u, (uint32_t)(state_floats(D) + m - 1) * pbytes);
-        } else {
-            const InT *tag = nullptr;
-            v = load_in(r_feats, tag, n, m - 1, jj);
+    float p[RPT][D];
+#pragma unroll
+    for (int r = 0; r < RPT; r++)
+#pragma unroll
+        for (int m = 1; m < D; m++) {
+            float v;
+            if (PAPER) {
+                v = bload(r_state, jr[r] * 4u, (uint32_t)(state_floats(D) + m - 1) * pbytes);
+            } else {
+                const InT *tag = nullptr;
+                v = load_in(r_feats, tag, n, m - 1, jr[r]);
+            }
+            p[r][m] = finite(v) ? v : 0.0f;
         }
-        return finite(v) ? v : 0.0f;
-    };
 
     {
         float g[kBlendSlots][3];
@@ -680,6 +684,9 @@ blend_kernel(const BlendArgs a)
         weights(std::false_type{});
     else
         weights(std::true_type{});
+    float inv_den[RPT];
+#pragma unroll
+    for (int r = 0; r < RPT; r++) inv_den[r] = 1.0f / den[r];
 
     float outc[RPT][3];
     // kept rolled: unrolled, the compiler hoists every channel's loads and
@@ -739,8 +746,8 @@ blend_kernel(const BlendArgs a)
         for (int r = 0; r < RPT; r++) {
             float yv = acc[r][0];  // p_0 = 1
 #pragma unroll
-            for (int m = 1; m < D; m++) yv = fmaf(pred_entry(jr[r], m), acc[r][m], yv);
-            outc[r][c] = yv / den[r];
+            for (int m = 1; m < D; m++) yv = fmaf(p[r][m], acc[r][m], yv);
+            outc[r][c] = yv * inv_den[r];
         }
     }
     const Rsrc r_out = array_rsrc(a.out, 3u * n * 4u);

@@ -48,6 +48,23 @@ def g1(gpu: np.ndarray, ref: np.ndarray, scale=None) -> float:
     return float(np.max(np.abs(gpu.astype(np.float64) - ref) / den))
 
 
+def blend_scale(beta_ref: np.ndarray, p: np.ndarray) -> np.ndarray:
+    """Term scale of the 5x5 blend: max over the window (inside the image)
+    of sum_m |p_i,m beta_k,c,m|, the magnitude of the terms of the
+    predictions the blend averages.  beta_ref (3,d,H,W), p (d,H,W)."""
+    _, d, H, W = beta_ref.shape
+    ab, ap = np.abs(beta_ref), np.abs(p)
+    s = np.zeros((3, H, W))
+    for dy in range(-2, 3):
+        for dx in range(-2, 3):
+            sh = np.zeros_like(ab)
+            ys, yd = slice(max(0, dy), H + min(0, dy)), slice(max(0, -dy), H + min(0, -dy))
+            xs, xd = slice(max(0, dx), W + min(0, dx)), slice(max(0, -dx), W + min(0, -dx))
+            sh[:, :, yd, xd] = ab[:, :, ys, xs]
+            s = np.maximum(s, np.einsum("dhw,cdhw->chw", ap, sh))
+    return s
+
+
 def unpack_P(P_packed: np.ndarray, d: int) -> np.ndarray:
     """(d(d+1)/2, H, W) upper triangle, row-major -> (d, d, H, W) symmetric."""
     H, W = P_packed.shape[1:]

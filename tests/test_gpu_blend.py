@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import synth
-from parity import G1_TOL, Pair, g1, log, predictor, to_dev
+from parity import G1_TOL, Pair, blend_scale, g1, log, predictor, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -27,21 +27,6 @@ def _gpu():
     from paper_2106_08034_amd import wrls
     wrls.lib()
     yield
-
-
-def blend_scale(beta_ref, p):
-    """max over the 5x5 window (inside the image) of sum_m |p_i,m beta_k,c,m|."""
-    _, d, H, W = beta_ref.shape
-    ab, ap = np.abs(beta_ref), np.abs(p)
-    s = np.zeros((3, H, W))
-    for dy in range(-2, 3):
-        for dx in range(-2, 3):
-            sh = np.zeros_like(ab)
-            ys, yd = slice(max(0, dy), H + min(0, dy)), slice(max(0, -dy), H + min(0, -dy))
-            xs, xd = slice(max(0, dx), W + min(0, dx)), slice(max(0, -dx), W + min(0, -dx))
-            sh[:, :, yd, xd] = ab[:, :, ys, xs]
-            s = np.maximum(s, np.einsum("dhw,cdhw->chw", ap, sh))
-    return s
 
 
 def _blend_check(pair, feats, out_t, sigma_s, sigma_r, tag):
