@@ -1,0 +1,141 @@
+"""The spatial blend and the paper-mode step at the largest image a stream
+accepts (state copy just below 4 GiB, so the highest 32-bit buffer offsets
+are used), against the FP64 oracle on sampled windows.
+
+The GPU runs the whole image.  Its state is exported and loaded into small
+oracles covering each window plus a margin (placed at the crop's origin, so
+that source positions round as in the full image); the oracle then takes
+the same next step and/or blend on identical state and inputs.  Only window
+pixels are compared: they lie at least 4 pixels inside their crop (beyond
+the reach of the reprojection, the 3x3 clamp and the 5x5 blend) unless the
+crop edge is the image edge, where both sides see the same border.
+"""
+import numpy as np
+import pytest
+
+from parity import G1_TOL, blend_scale, g1, log, predictor, term_scale, unpack_P
+
+pytestmark = pytest.mark.gpu
+
+MARGIN = 4
+WIN_W, WIN_H = 28, 6
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_2106_08034_amd import wrls
+    wrls.lib()
+    yield
+
+
+def _max_side(d, mode):
+    from paper_2106_08034_amd import wrls
+    side = 16384
+    while True:
+        p = wrls.make_params(side, side, d, weight_mode=mode)
+        if wrls.wrls_params_validate(p) == 0:
+            return side
+        side -= 16
+
+
+def _windows(side):
+    wins = [(0, 0), (side - WIN_W, side - WIN_H), (side // 2 + 5, side // 3 + 1), (5, side - 10)]
+    out = []
+    for (x0, y0) in wins:
+        cx0, cy0 = max(0, x0 - MARGIN), max(0, y0 - MARGIN)
+        cx1, cy1 = min(side, x0 + WIN_W + MARGIN), min(side, y0 + WIN_H + MARGIN)
+        out.append(((x0, y0), (cx0, cy0, cx1, cy1)))
+    return out
+
+
+def _crop(t, c):
+    cx0, cy0, cx1, cy1 = c
+    return t[..., cy0:cy1, cx0:cx1].cpu().numpy()
+
+
+def test_blend_at_maximum_size_d10_fp16():
+    import oracle
+    import torch
+    from paper_2106_08034_amd import wrls
+    d = 10
+    side = _max_side(d, "invvar")
+    log("case blend max size %dx%d d=10 FP16" % (side, side))
+    g = torch.Generator(device="cuda").manual_seed(11)
+    s = wrls.Stream(side, side, d, in_dtype="f16")
+    feats = torch.rand((d - 1, side, side), device="cuda", generator=g).half()
+    out = torch.empty((3, side, side), device="cuda")
+    for t in range(2):
+        color = (torch.rand((3, side, side), device="cuda", generator=g) * 1.5).half()
+        var = torch.rand((side, side), device="cuda", generator=g) * 0.2 + 0.01
+        mot = torch.empty((2, side, side), device="cuda")
+        mot[0].fill_(1.3)
+        mot[1].fill_(-0.6)
+        s.step(color, feats, var, mot, out=out)
+    fin = s.blend(feats, out, 1.5, 0.15)
+    P, B = s.get_state()
+    torch.cuda.synchronize()
+    for (x0, y0), c in _windows(side):
+        cx0, cy0, cx1, cy1 = c
+        o = oracle.Oracle(cx1 - cx0, cy1 - cy0, d, origin=(cx0, cy0))
+        Bc = _crop(B, c)
+        o.set_state(unpack_P(_crop(P, c), d), Bc, frames=2)
+        fc = _crop(feats, c).astype(np.float64)
+        ref = o.blend(fc, 1.5, 0.15)
+        wy, wx = slice(y0 - cy0, y0 - cy0 + WIN_H), slice(x0 - cx0, x0 - cx0 + WIN_W)
+        got = fin[:, y0:y0 + WIN_H, x0:x0 + WIN_W].cpu().numpy()
+        scale = blend_scale(Bc.astype(np.float64), predictor(fc))
+        e = g1(got, ref[:, wy, wx], scale[:, wy, wx])
+        log("  window (%d, %d): blend error %.3g" % (x0, y0, e))
+        assert e <= G1_TOL, ((x0, y0), e)
+    s.close()
+    torch.cuda.synchronize()
+
+
+def test_paper_step_and_blend_at_maximum_size():
+    import oracle
+    import torch
+    from paper_2106_08034_amd import wrls
+    side = _max_side(4, "paper")
+    log("case paper max size %dx%d" % (side, side))
+    g = torch.Generator(device="cuda").manual_seed(12)
+    s = wrls.Stream(side, side, 4, weight_mode="paper")
+
+    def frame():
+        color = torch.rand((3, side, side), device="cuda", generator=g) * 1.5
+        mot = torch.empty((2, side, side), device="cuda")
+        mot[0].fill_(1.3)
+        mot[1].fill_(0.6)
+        holes = torch.rand((side, side), device="cuda", generator=g) < 0.02
+        mot[:, holes] = float("nan")
+        return color, mot
+
+    c1, m1 = frame()
+    s.step(c1, None, None, m1)
+    P, B = s.get_state()
+    z = s.get_history()
+    c2, m2 = frame()
+    out = s.step(c2, None, None, m2)
+    fin = s.blend(None, out, 1.5, 0.15)
+    torch.cuda.synchronize()
+    for (x0, y0), c in _windows(side):
+        cx0, cy0, cx1, cy1 = c
+        o = oracle.Oracle(cx1 - cx0, cy1 - cy0, 4, wmode=oracle.W_PAPER, origin=(cx0, cy0),
+                          eps=float(np.float32(1e-4)))
+        o.set_state(unpack_P(_crop(P, c), 4), _crop(B, c), frames=1)
+        o.set_history(_crop(z, c))
+        ref = o.step(_crop(c2, c), None, None, _crop(m2, c))
+        wy, wx = slice(y0 - cy0, y0 - cy0 + WIN_H), slice(x0 - cx0, x0 - cx0 + WIN_W)
+        beta = o.get_beta()
+        p = predictor(o.get_history())
+        got = out[:, y0:y0 + WIN_H, x0:x0 + WIN_W].cpu().numpy()
+        e = g1(got, ref[:, wy, wx], term_scale(beta, p)[:, wy, wx])
+        ref_b = o.blend(None, 1.5, 0.15)
+        got_b = fin[:, y0:y0 + WIN_H, x0:x0 + WIN_W].cpu().numpy()
+        eb = g1(got_b, ref_b[:, wy, wx], blend_scale(beta, p)[:, wy, wx])
+        log("  window (%d, %d): step error %.3g, blend error %.3g" % (x0, y0, e, eb))
+        assert e <= G1_TOL and eb <= G1_TOL, ((x0, y0), e, eb)
+    s.close()
+    torch.cuda.synchronize()
