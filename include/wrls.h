@@ -168,12 +168,17 @@ int64_t wrls_frames(const wrls_stream *s);
 
 /* One frame (Sec. 5.2-5.3).
  *   color    [3][H][W]    in_dtype   noisy colour I~(t), linear HDR
- *   features [d-1][H][W]  in_dtype   predictor entries 1..d-1 (NULL iff d = 1)
- *   variance [H][W]       float      per-pixel noise variance (NULL allowed
- *                                    only with WRLS_W_ONE)
+ *   features [d-1][H][W]  in_dtype   predictor entries 1..d-1 (NULL for d = 1;
+ *                                    not used in WRLS_W_PAPER mode)
+ *   variance [H][W]       float      per-pixel noise variance (required by
+ *                                    WRLS_W_INVVAR only)
  *   motion   [2][H][W]    float      vx plane then vy plane; NULL = zero
  *   out      [3][H][W]    float      denoised colour, written
- * Reads the state of the previous frame and writes this frame's state. */
+ * All are dense device arrays, aligned to their element size, caller-owned
+ * and valid until the step completes on the stream; out must not overlap an
+ * input (other pixels' neighbourhoods are read while outputs are written).
+ * Reads the state of the previous frame and writes this frame's state.
+ * WRLS_EINVAL for a missing or misaligned array, or out equal to an input. */
 wrls_status wrls_step(wrls_stream *s, const void *color, const void *features,
                       const float *variance, const float *motion, float *out);
 
@@ -205,7 +210,9 @@ wrls_status wrls_set_state(wrls_stream *s, const float *P_packed, const float *b
  *   sigma_s   spatial width in pixels, sigma_r range width in colour units:
  *             > 0 with 1/(2 sigma^2) finite in binary32; +inf turns the
  *             factor off
- *   out       [3][H][W] FP32, device; must not alias temporal
+ *   out       [3][H][W] FP32, device; must not overlap temporal or the
+ *             features (the 5 x 5 halos are read while outputs are written)
+ * Arrays are aligned to their element size.
  * Stream-ordered on the stream's HIP stream; does not change the state.
  * WRLS_EINVAL before the first step or on bad arguments. */
 wrls_status wrls_blend(const wrls_stream *s, const void *features, const float *temporal,

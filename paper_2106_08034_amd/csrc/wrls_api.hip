@@ -50,6 +50,8 @@ int64_t plane_pitch(const wrls_params *p)
 
 wrls::TileShape default_tile() { return wrls::TileShape{7, 256, 0}; }
 
+bool aligned(const void *ptr, size_t bytes) { return ((uintptr_t)ptr % bytes) == 0; }
+
 // State entries per pixel of a stream: the model, plus the history in paper mode.
 int stream_state_floats(const wrls_params *p)
 {
@@ -274,6 +276,14 @@ wrls_status frame_args(const wrls_stream *s, const void *color, const void *feat
         return fail(WRLS_EINVAL, "features is NULL with d = %d", p.d);
     if (p.weight_mode == WRLS_W_INVVAR && !variance)
         return fail(WRLS_EINVAL, "variance is NULL with inverse-variance weights");
+    const size_t in_size = p.in_dtype == WRLS_F16 ? 2 : 4;
+    if (!aligned(color, in_size) || (features && !aligned(features, in_size)))
+        return fail(WRLS_EINVAL, "color and features need %zu-byte alignment", in_size);
+    if (!aligned(variance, 4) || !aligned(motion, 4) || !aligned(out, 4))
+        return fail(WRLS_EINVAL, "variance, motion and out need 4-byte alignment");
+    if ((const void *)out == color || (const void *)out == features ||
+        (const void *)out == variance || (const void *)out == motion)
+        return fail(WRLS_EINVAL, "out must not alias an input");
     *a = wrls::FrameArgs{};
     a->color = color;
     a->feats = paper ? nullptr : features;
@@ -331,6 +341,9 @@ wrls_status wrls_blend(const wrls_stream *s, const void *features, const float *
     if (s->frames <= 0) return fail(WRLS_EINVAL, "no state yet: step a frame before blending");
     if (!temporal || !out) return fail(WRLS_EINVAL, "temporal and out are required");
     if (out == temporal) return fail(WRLS_EINVAL, "out must not alias temporal (its halo is read)");
+    const size_t in_size = p.in_dtype == WRLS_F16 ? 2 : 4;
+    if ((features && !aligned(features, in_size)) || !aligned(temporal, 4) || !aligned(out, 4))
+        return fail(WRLS_EINVAL, "features need %zu-byte alignment, temporal and out 4-byte", in_size);
     if (p.d > 1 && !paper && !features)
         return fail(WRLS_EINVAL, "features is NULL with d = %d", p.d);
     // +inf turns a factor off (1/(2 sigma^2) = 0); 1/(2 sigma^2) must be

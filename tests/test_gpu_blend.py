@@ -157,5 +157,14 @@ def test_blend_leaves_state_alone_and_rejects_bad_arguments():
         assert ei.value.status == wrls.WRLS_EINVAL
     with pytest.raises(wrls.WrlsError):            # output aliasing the guide
         s.blend(feats, out, 1.5, 0.1, out=out)
+    # misaligned arrays are rejected on the host, before any launch
+    L = wrls.lib()
+    odd = fin.data_ptr() + 2
+    assert L.wrls_blend(s.handle, feats.data_ptr(), out.data_ptr(), 1.5, 0.1, odd) == wrls.WRLS_EINVAL
+    assert L.wrls_step(s.handle, color.data_ptr(), feats.data_ptr() + 1, var.data_ptr(), None,
+                       out.data_ptr()) == wrls.WRLS_EINVAL
+    assert L.wrls_step(s.handle, color.data_ptr(), feats.data_ptr(), var.data_ptr(), None,
+                       color.data_ptr()) == wrls.WRLS_EINVAL
+    assert s.frames == 1
     assert torch.isfinite(fin).all()
     s.close()
