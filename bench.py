@@ -346,8 +346,8 @@ def main():
         print("copied 10 x %d MiB" % args.copy_calibration, flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build measures one GPU's share "
-              "(a stream or image band per GPU needs no collective); --gpus %d is not supported"
+        print("bench.py runs on exactly one GPU: it measures one GPU's share of the work "
+              "(a stream or an image band per GPU needs no collective); --gpus %d is not supported"
               % args.gpus, file=sys.stderr)
         sys.exit(2)
 

@@ -54,7 +54,7 @@ typedef enum {
     WRLS_EINVAL = -1,        /* bad argument: null pointer, bad size, bad mode */
     WRLS_ENOMEM = -2,        /* device allocation failed */
     WRLS_EHIP = -3,          /* a HIP runtime call failed; text in wrls_last_error() */
-    WRLS_EUNSUPPORTED = -4   /* valid request this build does not implement */
+    WRLS_EUNSUPPORTED = -4   /* valid request the library does not implement */
 } wrls_status;
 
 typedef enum { WRLS_F32 = 0, WRLS_F16 = 1 } wrls_dtype;
