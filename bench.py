@@ -53,8 +53,12 @@ def blend_bytes_per_pixel(d: int, in_bytes: int, paper: bool = False) -> int:
 
 
 def kernel_source_hash() -> str:
-    src = os.path.join(ROOT, "paper_2106_08034_amd", "csrc", "wrls_kernels.hip")
-    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    """Identifies the device code: the kernels and the internal header whose
+    constants (tile shapes, plane alignment) they are compiled with."""
+    h = hashlib.sha256()
+    for f in ("wrls_kernels.hip", "wrls_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2106_08034_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def load_traffic(workload: str, kernel: str = ""):
