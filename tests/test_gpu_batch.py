@@ -122,24 +122,41 @@ def test_stream_in_caller_memory_equals_library_allocation():
     torch.cuda.synchronize()
 
 
-def test_full_size_c4_mix_batch_equals_alone():
+@pytest.mark.parametrize("shape", [None, (8, 256, 0)])
+def test_full_size_c4_mix_batch_equals_alone(shape):
     """The 16-stream mix at its real resolutions (640x480 .. 2560x1440,
     FP16, d = 8) for a few frames: the batched graph replay gives every
-    stream the bits of its own launch."""
+    stream the bits of its own launch, with the default tile and with the
+    256 x 1 tile the benchmark's autotuner picks; the smallest stream also
+    matches the oracle (G1)."""
+    import oracle
     import torch
     from paper_2106_08034_amd import wrls
     T = 3
     wls = _mix(1.0, T)
-    log("case c4 full mix: " + ", ".join("%dx%d" % (w.width, w.height) for w in wls))
+    log("case c4 full mix %s: " % (shape,) + ", ".join("%dx%d" % (w.width, w.height) for w in wls))
     b = wrls.Batch(len(wls), 8, "f16")
+    if shape is not None:
+        b.set_tile(*shape)
+    small = min(range(len(wls)), key=lambda i: wls[i].width * wls[i].height)
+    o = oracle.Oracle(wls[small].width, wls[small].height, 8)
     alone = [wrls.Stream(wl.width, wl.height, 8, in_dtype="f16", hip_stream=b.hip_stream) for wl in wls]
     mixed = [wrls.Stream(wl.width, wl.height, 8, in_dtype="f16", hip_stream=b.hip_stream) for wl in wls]
+    if shape is not None:
+        for s in alone:
+            s.set_tile(shape[0], shape[1], shape[2])
     srcs = [synth.FrameSource(wl) for wl in wls]
     for t in range(T):
-        fr = [_dev(s.next()) for s in srcs]
+        host = [s.next() for s in srcs]
+        fr = [_dev(h) for h in host]
         with torch.cuda.stream(torch.cuda.ExternalStream(b.hip_stream)):
             outs_a = [s.step(*fr[i]) for i, s in enumerate(alone)]
             outs_b = b.step(mixed, fr)
         torch.cuda.synchronize()
         for i in range(len(wls)):
             assert torch.equal(outs_a[i], outs_b[i]), (t, wls[i].name)
+        h = host[small]
+        ref = o.step(h.color, h.feats, h.var, h.motion)
+        e = g1(outs_b[small].cpu().numpy(), ref, term_scale(o.get_beta(), predictor(h.feats)))
+        log("  frame %d: %s vs oracle G1 %.3g" % (t, wls[small].name, e))
+        assert e <= G1_TOL, e
