@@ -472,27 +472,46 @@ def main():
         # first n_cpu frames of the sequence until about 10 s of CPU work
         import oracle
         n_cpu = args.cpu_frames or wl.frames
+
+        def make_oracle():
+            if paper:
+                return oracle.Oracle(wl.width, wl.height, 4, lam=0.98, wmode=oracle.W_PAPER)
+            return oracle.Oracle(wl.width, wl.height, wl.d, lam=0.98)
+
+        def step_oracle(o, f):
+            if paper:
+                o.step(f.color, None, None, f.motion)
+            else:
+                o.step(f.color, f.feats, f.var, f.motion)
+
         passes = 0
         frames_done = 0
         tc = time.perf_counter()
         while passes < 8 and (passes == 0 or time.perf_counter() - tc < 10.0):
-            if paper:
-                o = oracle.Oracle(wl.width, wl.height, 4, lam=0.98, wmode=oracle.W_PAPER)
-            else:
-                o = oracle.Oracle(wl.width, wl.height, wl.d, lam=0.98)
+            o = make_oracle()
             for f in host_frames[:n_cpu]:
-                if paper:
-                    o.step(f.color, None, None, f.motion)
-                else:
-                    o.step(f.color, f.feats, f.var, f.motion)
+                step_oracle(o, f)
             del o
             passes += 1
             frames_done += n_cpu
         cpu_s = time.perf_counter() - tc
+        cores = oracle.threads()
         cpu = {"value": round(frames_done * npix / cpu_s / 1e6, 3), "unit": "Mpix/s",
-               "cores": oracle.threads(), "kind": "oracle",
+               "cores": cores, "kind": "oracle",
                "sample": "FP64 C oracle (OpenMP over rows), %d pass(es) over the first %d frames "
                          "of the same %s sequence, %.1f s" % (passes, n_cpu, wl.name, cpu_s)}
+        # the same oracle on one thread, over the first 3 frames
+        oracle.set_threads(1)
+        n1 = min(3, n_cpu)
+        t1 = time.perf_counter()
+        o = make_oracle()
+        for f in host_frames[:n1]:
+            step_oracle(o, f)
+        del o
+        s1 = time.perf_counter() - t1
+        oracle.set_threads(cores)
+        cpu["single_thread"] = {"value": round(n1 * npix / s1 / 1e6, 3), "unit": "Mpix/s",
+                                "sample": "the first %d frames, %.1f s" % (n1, s1)}
 
     line = {
         "metric": "denoised Mpix/s (wRLS step) + % HBM roofline",

@@ -68,6 +68,7 @@ def _load():
     lib.oracle_set_history.argtypes = [ctypes.c_void_p, dp]
     lib.oracle_threads.restype = ctypes.c_int
     lib.oracle_threads.argtypes = []
+    lib.oracle_set_threads.argtypes = [ctypes.c_int]
     lib.oracle_step.restype = ctypes.c_int
     lib.oracle_step.argtypes = [ctypes.c_void_p, dp, dp, dp, dp, dp, dp,
                                 ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
@@ -83,6 +84,11 @@ def _load():
 def threads() -> int:
     """OpenMP threads the oracle's per-row loop uses."""
     return int(_load().oracle_threads())
+
+
+def set_threads(n: int) -> None:
+    """Sets the OpenMP threads of the oracle's per-row loops."""
+    _load().oracle_set_threads(int(n))
 
 
 def _f64(a, shape):

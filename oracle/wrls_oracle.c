@@ -161,6 +161,9 @@ void oracle_set_paper_params(oracle *o, double alpha, double h, double eps)
 /* Threads the per-row loop of oracle_step runs on. */
 int oracle_threads(void) { return omp_get_max_threads(); }
 
+/* Threads of the per-row loops from now on (n >= 1). */
+void oracle_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+
 /*
  * Reprojection (Sec. 5.3; Table 2 defines pi(v_j) = j + v_j as the pixel
  * position in the preceding frame).  Returns 1 and fills P, beta from the

@@ -401,3 +401,23 @@ def test_crop_with_origin_reproduces_full_image_bitwise(axis):
     assert np.array_equal(out_crop[keep], ref)
     # without the origin, binary32 rounding of the source position differs
     assert not np.array_equal(out_local[keep], ref)
+
+
+def test_results_do_not_depend_on_thread_count():
+    """Pixels are independent: one thread and many give the same bits."""
+    rng = np.random.default_rng(77)
+    H, W, d = 9, 23, 4
+    frames = [(rng.uniform(0, 1, (3, H, W)), rng.uniform(0, 1, (d - 1, H, W)),
+               np.exp(-3 + rng.standard_normal((H, W))), rng.uniform(-1, 1, (2, H, W)))
+              for _ in range(4)]
+    outs = []
+    n0 = oracle.threads()
+    try:
+        for n in (1, max(2, n0)):
+            oracle.set_threads(n)
+            o = oracle.Oracle(W, H, d)
+            outs.append([o.step(*f) for f in frames] + [o.blend(frames[-1][1], 1.5, 0.2)])
+    finally:
+        oracle.set_threads(n0)
+    for a, b in zip(*outs):
+        np.testing.assert_array_equal(a, b)
