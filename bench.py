@@ -53,10 +53,11 @@ def blend_bytes_per_pixel(d: int, in_bytes: int, paper: bool = False) -> int:
 
 
 def kernel_source_hash() -> str:
-    """Identifies the device code: the kernels and the internal header whose
-    constants (tile shapes, plane alignment) they are compiled with."""
+    """Identifies the code that shapes a launch's memory traffic: the kernels,
+    the internal header whose constants they compile with, and the host side
+    that lays out the state (plane pitch) and launches them."""
     h = hashlib.sha256()
-    for f in ("wrls_kernels.hip", "wrls_internal.h"):
+    for f in ("wrls_kernels.hip", "wrls_internal.h", "wrls_api.hip"):
         h.update(open(os.path.join(ROOT, "paper_2106_08034_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 

@@ -78,13 +78,21 @@ def test_state_copy_limit_4gib():
     assert "4 GiB" in wrls.wrls_last_error()
     p = wrls.wrls_params_default(3840, 2160, 10)
     assert wrls.wrls_params_validate(p) == wrls.WRLS_OK
-    # the largest square image at d = 10 whose state copy fits
+    # the largest square image at d = 10 whose state copy fits; planes are
+    # an odd number of 256-byte units apart
     S = wrls.wrls_state_floats(10)
+
+    def pitch(npix):
+        q = (npix + 63) // 64
+        return (q + 1 - q % 2) * 64
+
     side = int(((2 ** 32 - 1) // (4 * S)) ** 0.5) // 8 * 8
-    while (side * side + 63) // 64 * 64 * 4 * S > 2 ** 32 - 1:
+    while pitch(side * side) * 4 * S > 2 ** 32 - 1:
         side -= 8
     assert wrls.wrls_params_validate(wrls.wrls_params_default(side, side, 10)) == wrls.WRLS_OK
     assert wrls.wrls_params_validate(wrls.wrls_params_default(side + 64, side + 64, 10)) == wrls.WRLS_EUNSUPPORTED
+    p = wrls.wrls_params_default(2560, 1440, 8)
+    assert wrls.wrls_stream_device_bytes(p) == 2 * 60 * 4 * pitch(2560 * 1440)
 
 
 def test_paper_mode_parameters():
