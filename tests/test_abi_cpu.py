@@ -92,7 +92,7 @@ def test_state_copy_limit_4gib():
     assert wrls.wrls_params_validate(wrls.wrls_params_default(side, side, 10)) == wrls.WRLS_OK
     assert wrls.wrls_params_validate(wrls.wrls_params_default(side + 64, side + 64, 10)) == wrls.WRLS_EUNSUPPORTED
     p = wrls.wrls_params_default(2560, 1440, 8)
-    assert wrls.wrls_stream_device_bytes(p) == 2 * 60 * 4 * pitch(2560 * 1440)
+    assert wrls.wrls_stream_device_bytes(p) == 2 * 60 * 4 * pitch(2560 * 1440) + 256
 
 
 def test_paper_mode_parameters():
