@@ -289,6 +289,7 @@ class Server:
         for s in self.sched.retire(float("inf")):
             self._close(s)
         lat = [x for s in self.sched.done for x in s.latencies]
+        waits = [s.admitted_at - s.arrival for s in self.sched.done if s.admitted_at is not None]
         return {
             "seconds": round(wall, 3),
             "steps": steps,
@@ -302,4 +303,7 @@ class Server:
             "sessions_waiting_at_end": len(self.sched.waiting),
             "sessions_rejected": len(self.sched.rejected),
             "max_concurrent": max_active,
+            # arrival to admission: grows when the HBM budget makes sessions queue
+            "admission_wait_p50_ms": round(percentile(waits, 50) * 1e3, 3) if waits else None,
+            "admission_wait_max_ms": round(max(waits) * 1e3, 3) if waits else None,
         }, recorded
