@@ -160,3 +160,50 @@ def test_full_size_c4_mix_batch_equals_alone(shape):
         e = g1(outs_b[small].cpu().numpy(), ref, term_scale(o.get_beta(), predictor(h.feats)))
         log("  frame %d: %s vs oracle G1 %.3g" % (t, wls[small].name, e))
         assert e <= G1_TOL, e
+
+
+def test_distinct_handles_from_two_host_threads():
+    """Distinct handles may be used concurrently: two host threads, each
+    stepping its own stream on its own HIP stream, give the bits of the
+    same streams run one after the other."""
+    import threading
+
+    import torch
+    from paper_2106_08034_amd import wrls
+    wls = _mix(0.25, 4, n=2)
+    frames = [[_dev(f) for f in _frames(wl, 4)] for wl in wls]
+    torch.cuda.synchronize()  # the uploads ran on the default stream
+    hip = [torch.cuda.Stream(), torch.cuda.Stream()]
+    seq_out = []
+    for i, wl in enumerate(wls):
+        s = wrls.Stream(wl.width, wl.height, 8, in_dtype="f16", hip_stream=hip[i].cuda_stream)
+        with torch.cuda.stream(hip[i]):
+            outs = [s.step(*f).clone() for f in frames[i]]
+        torch.cuda.synchronize()
+        seq_out.append(outs)
+        s.close()
+    par_out = [None, None]
+    errors = []
+
+    def run(i):
+        try:
+            wl = wls[i]
+            s = wrls.Stream(wl.width, wl.height, 8, in_dtype="f16", hip_stream=hip[i].cuda_stream)
+            with torch.cuda.stream(hip[i]):
+                outs = [s.step(*f).clone() for f in frames[i]]
+            hip[i].synchronize()
+            par_out[i] = outs
+            s.close()
+        except Exception as e:  # reported below, in the test's thread
+            errors.append(e)
+
+    ts = [threading.Thread(target=run, args=(i,)) for i in range(2)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    torch.cuda.synchronize()
+    assert not errors, errors
+    for i in range(2):
+        for a, b in zip(seq_out[i], par_out[i]):
+            assert torch.equal(a, b)
