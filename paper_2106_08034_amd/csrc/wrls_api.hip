@@ -54,7 +54,7 @@ int64_t plane_pitch(const wrls_params *p)
     return q * a;
 }
 
-wrls::TileShape default_tile() { return wrls::TileShape{7, 256, 0}; }
+wrls::TileShape default_tile() { return wrls::TileShape{7, 128, 0}; }
 
 bool aligned(const void *ptr, size_t bytes) { return ((uintptr_t)ptr % bytes) == 0; }
 
@@ -385,19 +385,17 @@ wrls_status wrls_get_state(const wrls_stream *s, float *P_packed, float *beta)
 {
     if (!s) return fail(WRLS_EINVAL, "stream handle is NULL");
     const int d = s->prm.d;
-    const size_t n = (size_t)s->prm.width * s->prm.height;
-    const float *src = s->state[s->cur];
-    const size_t spitch = (size_t)s->pitch * sizeof(float);
+    const int S = stream_state_floats(&s->prm);
+    const int64_t n = (int64_t)s->prm.width * s->prm.height;
     hipError_t e;
     if (P_packed) {
-        e = hipMemcpy2DAsync(P_packed, n * sizeof(float), src, spitch, n * sizeof(float),
-                             (size_t)wrls::packed_floats(d), hipMemcpyDeviceToDevice, s->st);
+        e = wrls::launch_convert(s->state[s->cur], P_packed, s->pitch, n, S, 0, wrls::packed_floats(d),
+                                 false, s->st);
         if (e != hipSuccess) return hip_fail(e, "state export (P)");
     }
     if (beta) {
-        e = hipMemcpy2DAsync(beta, n * sizeof(float), src + (size_t)wrls::packed_floats(d) * s->pitch,
-                             spitch, n * sizeof(float), (size_t)(3 * d), hipMemcpyDeviceToDevice,
-                             s->st);
+        e = wrls::launch_convert(s->state[s->cur], beta, s->pitch, n, S, wrls::packed_floats(d), 3 * d,
+                                 false, s->st);
         if (e != hipSuccess) return hip_fail(e, "state export (beta)");
     }
     return WRLS_OK;
@@ -410,20 +408,17 @@ wrls_status wrls_set_state(wrls_stream *s, const float *P_packed, const float *b
     if (!P_packed || !beta) return fail(WRLS_EINVAL, "P_packed and beta are both required");
     if (frames < 0) return fail(WRLS_EINVAL, "frames = %lld < 0", (long long)frames);
     const int d = s->prm.d;
-    const size_t n = (size_t)s->prm.width * s->prm.height;
-    float *dst = s->state[s->cur];
-    const size_t dpitch = (size_t)s->pitch * sizeof(float);
-    hipError_t e = hipMemcpy2DAsync(dst, dpitch, P_packed, n * sizeof(float), n * sizeof(float),
-                                    (size_t)wrls::packed_floats(d), hipMemcpyDeviceToDevice, s->st);
+    const int S = stream_state_floats(&s->prm);
+    const int64_t n = (int64_t)s->prm.width * s->prm.height;
+    hipError_t e = wrls::launch_convert(s->state[s->cur], const_cast<float *>(P_packed), s->pitch, n,
+                                        S, 0, wrls::packed_floats(d), true, s->st);
     if (e != hipSuccess) return hip_fail(e, "state import (P)");
-    e = hipMemcpy2DAsync(dst + (size_t)wrls::packed_floats(d) * s->pitch, dpitch, beta,
-                         n * sizeof(float), n * sizeof(float), (size_t)(3 * d),
-                         hipMemcpyDeviceToDevice, s->st);
+    e = wrls::launch_convert(s->state[s->cur], const_cast<float *>(beta), s->pitch, n, S,
+                             wrls::packed_floats(d), 3 * d, true, s->st);
     if (e != hipSuccess) return hip_fail(e, "state import (beta)");
     s->frames = frames;
     return WRLS_OK;
 }
-
 
 // ---- batched steps -------------------------------------------------------
 
@@ -702,10 +697,9 @@ wrls_status wrls_get_history(const wrls_stream *s, float *z)
     if (!s) return fail(WRLS_EINVAL, "stream handle is NULL");
     if (s->prm.weight_mode != WRLS_W_PAPER) return fail(WRLS_EINVAL, "the stream has no history");
     if (!z) return fail(WRLS_EINVAL, "z is NULL");
-    const size_t n = (size_t)s->prm.width * s->prm.height;
-    const float *src = s->state[s->cur] + (size_t)wrls::state_floats(s->prm.d) * s->pitch;
-    hipError_t e = hipMemcpy2DAsync(z, n * sizeof(float), src, (size_t)s->pitch * sizeof(float),
-                                    n * sizeof(float), 3, hipMemcpyDeviceToDevice, s->st);
+    const int64_t n = (int64_t)s->prm.width * s->prm.height;
+    hipError_t e = wrls::launch_convert(s->state[s->cur], z, s->pitch, n, stream_state_floats(&s->prm),
+                                        wrls::state_floats(s->prm.d), 3, false, s->st);
     if (e != hipSuccess) return hip_fail(e, "history export");
     return WRLS_OK;
 }
@@ -715,10 +709,10 @@ wrls_status wrls_set_history(wrls_stream *s, const float *z)
     if (!s) return fail(WRLS_EINVAL, "stream handle is NULL");
     if (s->prm.weight_mode != WRLS_W_PAPER) return fail(WRLS_EINVAL, "the stream has no history");
     if (!z) return fail(WRLS_EINVAL, "z is NULL");
-    const size_t n = (size_t)s->prm.width * s->prm.height;
-    float *dst = s->state[s->cur] + (size_t)wrls::state_floats(s->prm.d) * s->pitch;
-    hipError_t e = hipMemcpy2DAsync(dst, (size_t)s->pitch * sizeof(float), z, n * sizeof(float),
-                                    n * sizeof(float), 3, hipMemcpyDeviceToDevice, s->st);
+    const int64_t n = (int64_t)s->prm.width * s->prm.height;
+    hipError_t e = wrls::launch_convert(s->state[s->cur], const_cast<float *>(z), s->pitch, n,
+                                        stream_state_floats(&s->prm), wrls::state_floats(s->prm.d), 3,
+                                        true, s->st);
     if (e != hipSuccess) return hip_fail(e, "history import");
     return WRLS_OK;
 }

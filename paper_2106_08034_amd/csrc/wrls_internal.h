@@ -21,6 +21,27 @@ __host__ __device__ constexpr int packed_index(int d, int i, int m)
     return i * d - (i * (i - 1)) / 2 + (m - i);
 }
 
+// State layout of one copy (S entries per pixel, planes of `pitch` pixels):
+// the first 4 * (S / 4) entries sit in S / 4 planes of 16-byte vectors --
+// entry k at vector plane k / 4, element k % 4, so one 128-bit access moves
+// four entries of a pixel -- and the remaining S % 4 entries in scalar
+// planes after them.  The copy is S * pitch floats either way.
+__host__ __device__ constexpr int vec_planes(int S) { return S / 4; }
+// Byte offsets of entry k of pixel j: a per-pixel part (voff) and a
+// per-entry part (soff); the entry's address is base + soff + voff.
+__host__ __device__ inline void entry_offsets(int S, int k, uint32_t j, uint32_t pitch,
+                                              uint32_t &voff, uint32_t &soff)
+{
+    const int G = vec_planes(S);
+    if (k < 4 * G) {
+        voff = j * 16u + (uint32_t)(k % 4) * 4u;
+        soff = (uint32_t)(k / 4) * pitch * 16u;
+    } else {
+        voff = j * 4u;
+        soff = (uint32_t)(4 * G) * pitch * 4u + (uint32_t)(k - 4 * G) * pitch * 4u;
+    }
+}
+
 // Everything one launch of the per-frame kernel needs for one image.
 struct FrameArgs {
     const void *color;      // [3][H][W] float or _Float16
@@ -28,10 +49,10 @@ struct FrameArgs {
     const float *var;       // [H][W] or null (unit weights)
     const float *motion;    // [2][H][W] or null (zero motion)
     float *out;             // [3][H][W]
-    const float *state_in;  // S planes of `pitch` floats (previous frame)
-    float *state_out;       // S planes of `pitch` floats (this frame)
+    const float *state_in;  // state copy of the previous frame (layout above)
+    float *state_out;       // state copy of this frame
     int32_t W, H;
-    int64_t pitch;          // floats between state planes
+    int64_t pitch;          // pixels per state plane
     float lambda, inv_lambda, p0, var_floor;
     float alpha, inv_h2, eps;  // paper mode: Eq. 12 history weight, 1/h^2 and eps of Eq. 13
     int32_t fresh;          // 1: no history (first frame)
@@ -68,7 +89,7 @@ struct BatchTable {
 // paragraph): the current state, the frame's predictor source, the step's
 // output as the range guide, and the output.
 struct BlendArgs {
-    const float *state;     // current state: S planes of `pitch` floats
+    const float *state;     // current state copy (layout above)
     const void *feats;      // [d-1][H][W] float or _Float16 (null in paper mode or d = 1)
     const float *guide;     // [3][H][W] output of the step (temporal prediction)
     float *out;             // [3][H][W]
@@ -90,6 +111,11 @@ constexpr int kBlendR = 2;
 // paper mode).
 hipError_t launch_reset(float *state, int64_t pitch, int64_t npix, int d, int S, float p0,
                         hipStream_t st);
+// Copies entries k0 .. k0 + count - 1 of every pixel between a state copy
+// (layout above) and caller planes [count][npix]; to_state selects the
+// direction.
+hipError_t launch_convert(float *state, float *planes, int64_t pitch, int64_t npix, int S, int k0,
+                          int count, bool to_state, hipStream_t st);
 hipError_t launch_step(int d, bool f16, const FrameArgs &a, TileShape ts, hipStream_t st);
 // The paper's own predictor and weight (d = 4, state with history).
 hipError_t launch_step_paper(bool f16, const FrameArgs &a, TileShape ts, hipStream_t st);

@@ -25,10 +25,6 @@ constexpr int kNumXcd = 8;
 // Cache policy of the streaming stores (state, output): non-temporal, so the
 // written lines do not displace the gathered previous-frame state in L2.
 constexpr int kStorePolicy = 2;
-// Planes whose bilinear taps are loaded together (see update_pixel).  Without
-// the grouping (and the scheduling barrier that keeps it) the compiler
-// serialises the d = 10 gather to a few loads in flight per wave.
-constexpr int kGatherGroup = 4;
 
 // Workgroups are dispatched to the XCDs round-robin (block b runs on XCD
 // b % 8).  Map block b to a tile index so that each XCD processes one
@@ -66,6 +62,25 @@ __device__ __forceinline__ void bstore(Rsrc r, uint32_t voff, uint32_t soff, flo
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff,
                                           (int)soff, kStorePolicy);
 }
+// 16-byte accesses (four state entries of one pixel) are ordinary global
+// loads and non-temporal stores of a 4-float vector: global_load_dwordx4 /
+// global_store_dwordx4.  (This compiler lowers the 128-bit raw-buffer-load
+// builtin to a single 32-bit load, so the buffer path is not used for them.)
+// Vector plane g of a state copy starts at float g * pitch * 4.
+// The pointers are marked global: state pointers read from a device table
+// (batched steps) would otherwise compile to flat accesses.
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) const f4_t gcf4_t;
+typedef __attribute__((address_space(1))) f4_t gf4_t;
+__device__ __forceinline__ gcf4_t *vec_plane(const float *state, int g, uint32_t pitch)
+{
+    return (gcf4_t *)(state + (size_t)g * pitch * 4u);
+}
+__device__ __forceinline__ gf4_t *vec_plane(float *state, int g, uint32_t pitch)
+{
+    return (gf4_t *)(state + (size_t)g * pitch * 4u);
+}
+
 // Element j of plane `plane` of an input array of planes of n values.
 __device__ __forceinline__ float load_in(Rsrc r, const float *, uint32_t n, int plane, uint32_t j)
 {
@@ -83,11 +98,14 @@ __device__ __forceinline__ bool finite(float v) { return __builtin_isfinite(v); 
 // Reprojection (Sec. 5.3, Table 2: pi(v_j) = j + v_j in the previous frame):
 // the NS state entries of pixel (x, y) gathered from the previous frame's
 // state at (x, y) + v.  Returns false when the pixel has no valid source
-// (first frame, non-finite motion, source outside the image).
+// (first frame, non-finite motion, source outside the image).  The vector
+// planes (four entries per 16-byte access) come first, then the scalar
+// remainder (entry_offsets).
 template <int NS>
 __device__ __forceinline__ bool gather_state(const FrameArgs &a, int x, int y, uint32_t j,
                                              uint32_t n, float (&st)[NS])
 {
+    constexpr int G = vec_planes(NS);
     if (a.fresh) return false;
     float vx = 0.0f, vy = 0.0f;
     if (a.motion) {
@@ -100,14 +118,22 @@ __device__ __forceinline__ bool gather_state(const FrameArgs &a, int x, int y, u
     // NaN fails every comparison and +-inf lands outside: both restart.
     if (!(sx >= 0.0f && sx <= (float)(a.W - 1) && sy >= 0.0f && sy <= (float)(a.H - 1)))
         return false;
-    const uint32_t pbytes = (uint32_t)a.pitch * 4u;
-    const Rsrc src = array_rsrc(a.state_in, (uint32_t)NS * pbytes);
+    const uint32_t pitch = (uint32_t)a.pitch;
+    const uint32_t sbase = (uint32_t)(4 * G) * pitch * 4u; // first scalar plane
+    const Rsrc src = array_rsrc(a.state_in, (uint32_t)NS * pitch * 4u);
     if (a.nearest) {
         const int xn = min((int)floorf(sx + 0.5f), a.W - 1);
         const int yn = min((int)floorf(sy + 0.5f), a.H - 1);
-        const uint32_t o = ((uint32_t)yn * (uint32_t)a.W + (uint32_t)xn) * 4u;
+        const uint32_t i = (uint32_t)yn * (uint32_t)a.W + (uint32_t)xn;
 #pragma unroll
-        for (int k = 0; k < NS; k++) st[k] = bload(src, o, (uint32_t)k * pbytes);
+        for (int g = 0; g < G; g++) {
+            const f4_t v = vec_plane(a.state_in, g, pitch)[i];
+#pragma unroll
+            for (int e = 0; e < 4; e++) st[4 * g + e] = v[e];
+        }
+#pragma unroll
+        for (int k = 4 * G; k < NS; k++)
+            st[k] = bload(src, i * 4u, sbase + (uint32_t)(k - 4 * G) * pitch * 4u);
         return true;
     }
     const float fx0 = floorf(sx), fy0 = floorf(sy);
@@ -115,34 +141,40 @@ __device__ __forceinline__ bool gather_state(const FrameArgs &a, int x, int y, u
     const int x0 = (int)fx0, y0 = (int)fy0;
     const int x1 = min(x0 + 1, a.W - 1), y1 = min(y0 + 1, a.H - 1);
     const uint32_t W = (uint32_t)a.W;
-    const uint32_t o00 = ((uint32_t)y0 * W + (uint32_t)x0) * 4u;
-    const uint32_t o10 = ((uint32_t)y0 * W + (uint32_t)x1) * 4u;
-    const uint32_t o01 = ((uint32_t)y1 * W + (uint32_t)x0) * 4u;
-    const uint32_t o11 = ((uint32_t)y1 * W + (uint32_t)x1) * 4u;
-    // Bilinear in nested-lerp form (exact for a constant field).  Entries go
-    // in groups of kGatherGroup: the group's 4 * kGatherGroup loads are issued
-    // back to back, so many are in flight per wave, before any is consumed.
+    const uint32_t i00 = (uint32_t)y0 * W + (uint32_t)x0, i10 = (uint32_t)y0 * W + (uint32_t)x1;
+    const uint32_t i01 = (uint32_t)y1 * W + (uint32_t)x0, i11 = (uint32_t)y1 * W + (uint32_t)x1;
+    // Bilinear in nested-lerp form (exact for a constant field).  One vector
+    // plane per batch: its four taps (16 entries) are issued back to back,
+    // behind a scheduling barrier, before any is consumed.
 #pragma unroll
-    for (int k0 = 0; k0 < NS; k0 += kGatherGroup) {
-        float t00[kGatherGroup], t10[kGatherGroup], t01[kGatherGroup], t11[kGatherGroup];
+    for (int g = 0; g < G; g++) {
+        gcf4_t *pl = vec_plane(a.state_in, g, pitch);
+        const f4_t t00 = pl[i00], t10 = pl[i10], t01 = pl[i01], t11 = pl[i11];
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int g = 0; g < kGatherGroup; g++) {
-            if (k0 + g < NS) {
-                const uint32_t so = (uint32_t)(k0 + g) * pbytes;
-                t00[g] = bload(src, o00, so);
-                t10[g] = bload(src, o10, so);
-                t01[g] = bload(src, o01, so);
-                t11[g] = bload(src, o11, so);
-            }
+        for (int e = 0; e < 4; e++) {
+            const float top = fmaf(fx, t10[e] - t00[e], t00[e]);
+            const float bot = fmaf(fx, t11[e] - t01[e], t01[e]);
+            st[4 * g + e] = fmaf(fy, bot - top, top);
+        }
+    }
+    if constexpr (NS % 4 != 0) {
+        constexpr int R = NS - 4 * G;
+        float t00[R], t10[R], t01[R], t11[R];
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            const uint32_t so = sbase + (uint32_t)r * pitch * 4u;
+            t00[r] = bload(src, i00 * 4u, so);
+            t10[r] = bload(src, i10 * 4u, so);
+            t01[r] = bload(src, i01 * 4u, so);
+            t11[r] = bload(src, i11 * 4u, so);
         }
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int g = 0; g < kGatherGroup; g++) {
-            if (k0 + g < NS) {
-                const float top = fmaf(fx, t10[g] - t00[g], t00[g]);
-                const float bot = fmaf(fx, t11[g] - t01[g], t01[g]);
-                st[k0 + g] = fmaf(fy, bot - top, top);
-            }
+        for (int r = 0; r < R; r++) {
+            const float top = fmaf(fx, t10[r] - t00[r], t00[r]);
+            const float bot = fmaf(fx, t11[r] - t01[r], t01[r]);
+            st[4 * G + r] = fmaf(fy, bot - top, top);
         }
     }
     return true;
@@ -214,19 +246,26 @@ __device__ __forceinline__ void rls_update(float *P, float *B, const float (&p)[
     }
 }
 
-// Stores the NS state entries of pixel j and its output.
+// Stores the NS state entries of pixel j (vector planes, then the scalar
+// remainder) and its output.
 template <int NS>
 __device__ __forceinline__ void store_pixel(const FrameArgs &a, uint32_t j, uint32_t n,
                                             const float (&st)[NS], const float (&out)[3])
 {
-    const uint32_t pbytes = (uint32_t)a.pitch * 4u;
-    const Rsrc dst = array_rsrc(a.state_out, (uint32_t)NS * pbytes);
+    constexpr int G = vec_planes(NS);
+    const uint32_t pitch = (uint32_t)a.pitch;
+    const Rsrc dst = array_rsrc(a.state_out, (uint32_t)NS * pitch * 4u);
     const Rsrc r_out = array_rsrc(a.out, 3u * n * 4u);
-    const uint32_t oj = j * 4u;
 #pragma unroll
-    for (int k = 0; k < NS; k++) bstore(dst, oj, (uint32_t)k * pbytes, st[k]);
+    for (int g = 0; g < G; g++) {
+        const f4_t v = {st[4 * g], st[4 * g + 1], st[4 * g + 2], st[4 * g + 3]};
+        __builtin_nontemporal_store(v, vec_plane(a.state_out, g, pitch) + j);
+    }
+    const uint32_t sbase = (uint32_t)(4 * G) * pitch * 4u;
 #pragma unroll
-    for (int c = 0; c < 3; c++) bstore(r_out, oj, (uint32_t)c * n * 4u, out[c]);
+    for (int k = 4 * G; k < NS; k++) bstore(dst, j * 4u, sbase + (uint32_t)(k - 4 * G) * pitch * 4u, st[k]);
+#pragma unroll
+    for (int c = 0; c < 3; c++) bstore(r_out, j * 4u, (uint32_t)c * n * 4u, out[c]);
 }
 
 // The per-pixel update with supplied features.  D: predictor length; InT:
@@ -438,14 +477,37 @@ __global__ void __launch_bounds__(256) reset_kernel(float *state, int64_t pitch,
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
         const int k = (int)(e / npix);
-        const int64_t j = e - (int64_t)k * npix;
+        const uint32_t j = (uint32_t)(e - (int64_t)k * npix);
         float v = 0.0f;
         if (k < np) {
             // k is a diagonal entry iff it starts a row of the packed triangle
             for (int i = 0; i < d; i++)
                 if (k == packed_index(d, i, i)) v = p0;
         }
-        state[(size_t)k * pitch + j] = v;
+        uint32_t voff, soff;
+        entry_offsets(S, k, j, (uint32_t)pitch, voff, soff);
+        state[(soff + voff) / 4u] = v;
+    }
+}
+
+// Entries k0 .. k0 + count - 1 of every pixel between a state copy and
+// caller planes [count][npix].
+__global__ void __launch_bounds__(256) convert_kernel(float *state, float *planes, int64_t pitch,
+                                                      int64_t npix, int S, int k0, int count,
+                                                      int to_state)
+{
+    const int64_t total = (int64_t)count * npix;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(e / npix);
+        const uint32_t j = (uint32_t)(e - (int64_t)c * npix);
+        uint32_t voff, soff;
+        entry_offsets(S, k0 + c, j, (uint32_t)pitch, voff, soff);
+        const size_t i = (soff + voff) / 4u;
+        if (to_state)
+            state[i] = planes[e];
+        else
+            planes[e] = state[i];
     }
 }
 
@@ -574,9 +636,15 @@ blend_kernel(const BlendArgs a)
     const int lx = tid % kBlendTW, ly = (tid / kBlendTW) * RPT;  // first of the thread's rows
     const int x = x0 + lx;
     const uint32_t n = (uint32_t)a.W * (uint32_t)a.H;
-    const uint32_t pbytes = (uint32_t)a.pitch * 4u;
-    const Rsrc r_state = array_rsrc(a.state, (uint32_t)NS * pbytes);
+    const uint32_t pitch = (uint32_t)a.pitch;
+    const Rsrc r_state = array_rsrc(a.state, (uint32_t)NS * pitch * 4u);
     const Rsrc r_guide = array_rsrc(a.guide, 3u * n * 4u);
+    // entry k of pixel jj of the current state
+    auto state_entry = [&](int k, uint32_t jj) {
+        uint32_t voff, soff;
+        entry_offsets(NS, k, jj, pitch, voff, soff);
+        return bload(r_state, voff, soff);
+    };
 
     // Halo slots of this thread: global pixel index, or -1 outside the image.
     int hj[kBlendSlots];
@@ -608,7 +676,7 @@ blend_kernel(const BlendArgs a)
         for (int m = 1; m < D; m++) {
             float v;
             if (PAPER) {
-                v = bload(r_state, jr[r] * 4u, (uint32_t)(state_floats(D) + m - 1) * pbytes);
+                v = state_entry(state_floats(D) + m - 1, jr[r]);
             } else {
                 const InT *tag = nullptr;
                 v = load_in(r_feats, tag, n, m - 1, jr[r]);
@@ -704,8 +772,7 @@ blend_kernel(const BlendArgs a)
 #pragma unroll
                 for (int m = 0; m < 4 * NG; m++)
                     v[q][m] = (m < D && r0 + q < kBlendSlots && hj[r0 + q] >= 0)
-                                  ? bload(r_state, (uint32_t)hj[r0 + q] * 4u,
-                                          (uint32_t)(NP + c * D + m) * pbytes)
+                                  ? state_entry(NP + c * D + m, (uint32_t)hj[r0 + q])
                                   : 0.0f;
 #pragma unroll
             for (int q = 0; q < 2; q++) {
@@ -802,6 +869,19 @@ hipError_t launch_reset(float *state, int64_t pitch, int64_t npix, int d, int S,
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(reset_kernel, dim3((unsigned)blocks), dim3(256), 0, st, state, pitch, npix,
                        d, S, p0);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert(float *state, float *planes, int64_t pitch, int64_t npix, int S, int k0,
+                          int count, bool to_state, hipStream_t st)
+{
+    const int64_t total = (int64_t)count * npix;
+    if (total <= 0) return hipSuccess;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(convert_kernel, dim3((unsigned)blocks), dim3(256), 0, st, state, planes, pitch,
+                       npix, S, k0, count, to_state ? 1 : 0);
     return hipGetLastError();
 }
 
