@@ -587,6 +587,30 @@ hipError_t occupancy_batched_d(bool f16, int32_t block_threads, int *blocks_per_
         blocks_per_cu, reinterpret_cast<const void *>(&batch_kernel<D, float>), block_threads, 0);
 }
 
+// Entries K0 .. K0 + N - 1 of pixel jj of a state copy with NS entries per
+// pixel: the vector planes that hold them are read with 128-bit loads, the
+// entries past the vector planes with 32-bit ones.
+template <int NS, int K0, int N>
+__device__ __forceinline__ void load_entries(const float *state, Rsrc r_state, uint32_t pitch,
+                                             uint32_t jj, float (&out)[N])
+{
+    constexpr int G = vec_planes(NS);
+    constexpr int GA = K0 / 4;
+    constexpr int GB = (K0 + N - 1) / 4 < G ? (K0 + N - 1) / 4 : G - 1;
+    if constexpr (K0 < 4 * G) {
+        f4_t v[GB - GA + 1];
+#pragma unroll
+        for (int q = 0; q <= GB - GA; q++) v[q] = vec_plane(state, GA + q, pitch)[jj];
+#pragma unroll
+        for (int m = 0; m < N; m++)
+            if (K0 + m < 4 * G) out[m] = v[(K0 + m) / 4 - GA][(K0 + m) % 4];
+    }
+    const uint32_t sbase = (uint32_t)(4 * G) * pitch * 4u;
+#pragma unroll
+    for (int m = 0; m < N; m++)
+        if (K0 + m >= 4 * G) out[m] = bload(r_state, jj * 4u, sbase + (uint32_t)(K0 + m - 4 * G) * pitch * 4u);
+}
+
 // Spatial blend of neighbour-model predictions (Sec. 5.3, last paragraph),
 // after a step, over the current state.  Pixel i's final colour averages the
 // predictions p_i beta_k^T of the models k in the 5x5 window centred on i
@@ -619,7 +643,7 @@ constexpr int kBlendK = 2 * kBlendR + 1;  // window side
 // The occupancy hint caps registers: left alone, the scheduler keeps most of
 // a channel's LDS reads in flight and needs 168+ VGPRs at d = 8.
 template <int D, typename InT, bool PAPER>
-__global__ void __launch_bounds__(kBlendThreads) __attribute__((amdgpu_waves_per_eu(D <= 4 ? 5 : (D <= 7 ? 4 : (D <= 9 ? 3 : 2)))))
+__global__ void __launch_bounds__(kBlendThreads) __attribute__((amdgpu_waves_per_eu(D <= 2 ? 5 : (D <= 7 ? 4 : (D <= 9 ? 3 : 2)))))
 blend_kernel(const BlendArgs a)
 {
     constexpr int RPT = kBlendRPT;
@@ -764,27 +788,49 @@ blend_kernel(const BlendArgs a)
         if (c > 0) __syncthreads();  // the previous channel's reads are done
         // staged two slots at a time: the barrier keeps the compiler from
         // hoisting every slot's loads (and their registers) together
+        // The channel's entries, staged two halo slots at a time (the
+        // barrier keeps the compiler from hoisting every slot's loads, and
+        // their registers, together).  The channel is dispatched to a
+        // compile-time value so that every state offset is static.
+        // An opaque copy of the state pointer, made per channel: otherwise the
+        // compiler computes the addresses of all three channels' loads ahead
+        // of the loop and keeps them in registers.
+        const float *st = a.state;
+        asm volatile("" : "+s"(st));
+        auto stage = [&](auto cc) {
+            constexpr int C = decltype(cc)::value;
 #pragma unroll
-        for (int r0 = 0; r0 < kBlendSlots; r0 += 2) {
-            float v[2][4 * NG];
+            for (int r0 = 0; r0 < kBlendSlots; r0 += 2) {
+                float v[2][4 * NG];
 #pragma unroll
-            for (int q = 0; q < 2; q++)
+                for (int q = 0; q < 2; q++) {
 #pragma unroll
-                for (int m = 0; m < 4 * NG; m++)
-                    v[q][m] = (m < D && r0 + q < kBlendSlots && hj[r0 + q] >= 0)
-                                  ? state_entry(NP + c * D + m, (uint32_t)hj[r0 + q])
-                                  : 0.0f;
+                    for (int m = 0; m < 4 * NG; m++) v[q][m] = 0.0f;
+                    if (r0 + q < kBlendSlots && hj[r0 + q] >= 0) {
+                        float e[D];
+                        load_entries<NS, NP + C * D, D>(st, r_state, pitch, (uint32_t)hj[r0 + q], e);
 #pragma unroll
-            for (int q = 0; q < 2; q++) {
-                const int sl = tid + (r0 + q) * kBlendThreads;
-                if (r0 + q < kBlendSlots && sl < kBlendRN)
+                        for (int m = 0; m < D; m++) v[q][m] = e[m];
+                    }
+                }
 #pragma unroll
-                    for (int gq = 0; gq < NG; gq++)
-                        s_beta[gq][sl] = make_float4(v[q][4 * gq], v[q][4 * gq + 1], v[q][4 * gq + 2],
-                                                     v[q][4 * gq + 3]);
+                for (int q = 0; q < 2; q++) {
+                    const int sl = tid + (r0 + q) * kBlendThreads;
+                    if (r0 + q < kBlendSlots && sl < kBlendRN)
+#pragma unroll
+                        for (int gq = 0; gq < NG; gq++)
+                            s_beta[gq][sl] = make_float4(v[q][4 * gq], v[q][4 * gq + 1], v[q][4 * gq + 2],
+                                                         v[q][4 * gq + 3]);
+                }
+                __builtin_amdgcn_sched_barrier(0);
             }
-            __builtin_amdgcn_sched_barrier(0);
-        }
+        };
+        if (c == 0)
+            stage(std::integral_constant<int, 0>{});
+        else if (c == 1)
+            stage(std::integral_constant<int, 1>{});
+        else
+            stage(std::integral_constant<int, 2>{});
         __syncthreads();
         float acc[RPT][4 * NG];
 #pragma unroll
