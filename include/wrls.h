@@ -106,7 +106,7 @@ void wrls_params_default(wrls_params *p, int32_t width, int32_t height, int32_t 
 /* Checks a parameter block without touching the GPU: WRLS_OK or
  * WRLS_EINVAL / WRLS_EUNSUPPORTED with a message.  Besides the ranges noted
  * in wrls_params, one copy of a stream's state (wrls_state_floats(d) floats
- * per pixel, planes padded to 64 floats) must stay below 4 GiB: e.g. up to
+ * per pixel, pixels padded to whole 64-pixel chunks) must stay below 4 GiB: e.g. up to
  * about 17.9 Mpixel at d = 8 and 12.6 Mpixel at d = 10 (3840x2160 is 8.3). */
 wrls_status wrls_params_validate(const wrls_params *p);
 

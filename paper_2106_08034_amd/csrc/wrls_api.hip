@@ -13,7 +13,7 @@
 struct wrls_stream {
     wrls_params prm;
     hipStream_t st;
-    float *state[2];  // previous / current frame, S planes of `pitch` floats each
+    float *state[2];  // previous / current frame, S * pitch floats each (chunked layout)
     void *alloc;      // the single device allocation holding both copies
     bool owns_alloc;  // false: caller-owned memory (wrls_create_stream_in)
     int64_t pitch;
@@ -41,10 +41,9 @@ wrls_status hip_fail(hipError_t e, const char *what)
                 hipGetErrorString(e), (int)e);
 }
 
-// Floats between state planes: the pixel count rounded up to an odd number
-// of 256-byte units.  Planes of one pixel are read and written together; an
-// even (power-of-two-rich) stride puts their segments on the same memory
-// channels, which measured 4-6% slower at 1280x720, 2560x1440 and 4K.
+// Pixel slots of a state copy: the pixel count rounded up to an odd number
+// of 64-pixel chunks, so that the two copies of a stream (placed back to
+// back, 256 bytes apart) start an odd number of chunks apart.
 int64_t plane_pitch(const wrls_params *p)
 {
     const int64_t n = (int64_t)p->width * p->height;
@@ -174,7 +173,7 @@ wrls_status init_stream(const wrls_params *p, void *hip_stream, void *mem, bool 
     // apart (measured ~1% faster at 1080p)
     s->state[1] = s->state[0] + one + wrls::kPlaneAlign;
     const int64_t npix = (int64_t)p->width * p->height;
-    hipError_t e = wrls::launch_reset(s->state[0], s->pitch, npix, p->d, stream_state_floats(p),
+    hipError_t e = wrls::launch_reset(s->state[0], npix, p->d, stream_state_floats(p),
                                       1.0f / p->delta, s->st);
     if (e != hipSuccess) {
         delete s;
@@ -262,7 +261,7 @@ wrls_status wrls_reset(wrls_stream *s)
 {
     if (!s) return fail(WRLS_EINVAL, "stream handle is NULL");
     const int64_t npix = (int64_t)s->prm.width * s->prm.height;
-    hipError_t e = wrls::launch_reset(s->state[s->cur], s->pitch, npix, s->prm.d,
+    hipError_t e = wrls::launch_reset(s->state[s->cur], npix, s->prm.d,
                                       stream_state_floats(&s->prm), 1.0f / s->prm.delta, s->st);
     if (e != hipSuccess) return hip_fail(e, "reset launch");
     s->frames = 0;
@@ -389,12 +388,12 @@ wrls_status wrls_get_state(const wrls_stream *s, float *P_packed, float *beta)
     const int64_t n = (int64_t)s->prm.width * s->prm.height;
     hipError_t e;
     if (P_packed) {
-        e = wrls::launch_convert(s->state[s->cur], P_packed, s->pitch, n, S, 0, wrls::packed_floats(d),
+        e = wrls::launch_convert(s->state[s->cur], P_packed, n, S, 0, wrls::packed_floats(d),
                                  false, s->st);
         if (e != hipSuccess) return hip_fail(e, "state export (P)");
     }
     if (beta) {
-        e = wrls::launch_convert(s->state[s->cur], beta, s->pitch, n, S, wrls::packed_floats(d), 3 * d,
+        e = wrls::launch_convert(s->state[s->cur], beta, n, S, wrls::packed_floats(d), 3 * d,
                                  false, s->st);
         if (e != hipSuccess) return hip_fail(e, "state export (beta)");
     }
@@ -410,10 +409,10 @@ wrls_status wrls_set_state(wrls_stream *s, const float *P_packed, const float *b
     const int d = s->prm.d;
     const int S = stream_state_floats(&s->prm);
     const int64_t n = (int64_t)s->prm.width * s->prm.height;
-    hipError_t e = wrls::launch_convert(s->state[s->cur], const_cast<float *>(P_packed), s->pitch, n,
+    hipError_t e = wrls::launch_convert(s->state[s->cur], const_cast<float *>(P_packed), n,
                                         S, 0, wrls::packed_floats(d), true, s->st);
     if (e != hipSuccess) return hip_fail(e, "state import (P)");
-    e = wrls::launch_convert(s->state[s->cur], const_cast<float *>(beta), s->pitch, n, S,
+    e = wrls::launch_convert(s->state[s->cur], const_cast<float *>(beta), n, S,
                              wrls::packed_floats(d), 3 * d, true, s->st);
     if (e != hipSuccess) return hip_fail(e, "state import (beta)");
     s->frames = frames;
@@ -698,7 +697,7 @@ wrls_status wrls_get_history(const wrls_stream *s, float *z)
     if (s->prm.weight_mode != WRLS_W_PAPER) return fail(WRLS_EINVAL, "the stream has no history");
     if (!z) return fail(WRLS_EINVAL, "z is NULL");
     const int64_t n = (int64_t)s->prm.width * s->prm.height;
-    hipError_t e = wrls::launch_convert(s->state[s->cur], z, s->pitch, n, stream_state_floats(&s->prm),
+    hipError_t e = wrls::launch_convert(s->state[s->cur], z, n, stream_state_floats(&s->prm),
                                         wrls::state_floats(s->prm.d), 3, false, s->st);
     if (e != hipSuccess) return hip_fail(e, "history export");
     return WRLS_OK;
@@ -710,7 +709,7 @@ wrls_status wrls_set_history(wrls_stream *s, const float *z)
     if (s->prm.weight_mode != WRLS_W_PAPER) return fail(WRLS_EINVAL, "the stream has no history");
     if (!z) return fail(WRLS_EINVAL, "z is NULL");
     const int64_t n = (int64_t)s->prm.width * s->prm.height;
-    hipError_t e = wrls::launch_convert(s->state[s->cur], const_cast<float *>(z), s->pitch, n,
+    hipError_t e = wrls::launch_convert(s->state[s->cur], const_cast<float *>(z), n,
                                         stream_state_floats(&s->prm), wrls::state_floats(s->prm.d), 3,
                                         true, s->st);
     if (e != hipSuccess) return hip_fail(e, "history import");

@@ -8,8 +8,9 @@
 namespace wrls {
 
 constexpr int kMaxD = 10;
-// Per-pixel state planes are padded to a multiple of this many floats so
-// that every plane starts on a 256-byte boundary.
+// Pixels per chunk of the state layout (below); a state copy holds a whole
+// number of chunks, and the second copy of a stream starts this many floats
+// (256 bytes) past the end of the first.
 constexpr size_t kPlaneAlign = 64;
 
 __host__ __device__ constexpr int packed_floats(int d) { return d * (d + 1) / 2; }
@@ -21,24 +22,36 @@ __host__ __device__ constexpr int packed_index(int d, int i, int m)
     return i * d - (i * (i - 1)) / 2 + (m - i);
 }
 
-// State layout of one copy (S entries per pixel, planes of `pitch` pixels):
-// the first 4 * (S / 4) entries sit in S / 4 planes of 16-byte vectors --
-// entry k at vector plane k / 4, element k % 4, so one 128-bit access moves
-// four entries of a pixel -- and the remaining S % 4 entries in scalar
-// planes after them.  The copy is S * pitch floats either way.
+// State layout of one copy (S entries per pixel, `pitch` pixel slots, a
+// multiple of 64): pixels are grouped in chunks of 64 consecutive pixel
+// indices, and each chunk holds all S entries of its pixels contiguously
+// (S * 256 bytes).  Inside a chunk, the first 4 * (S / 4) entries form S / 4
+// groups of 16-byte vectors -- entry k of pixel l at group k / 4, vector l,
+// element k % 4, so one 128-bit access moves four entries of a pixel and a
+// wave's access to one group covers 1 KiB of consecutive bytes -- followed by
+// the remaining S % 4 entries as groups of 4-byte scalars.  The copy is
+// S * pitch floats.
 __host__ __device__ constexpr int vec_planes(int S) { return S / 4; }
+// Byte offset of pixel j's 16-byte slot (vector entries) and 4-byte slot
+// (scalar entries) relative to the start of an entry group of its chunk.
+__host__ __device__ inline uint32_t vslot(uint32_t j, int S) { return (j >> 6) * (uint32_t)S * 256u + (j & 63u) * 16u; }
+__host__ __device__ inline uint32_t sslot(uint32_t j, int S) { return (j >> 6) * (uint32_t)S * 256u + (j & 63u) * 4u; }
+// Byte offset, within a chunk, of vector group g and of scalar entry
+// 4 * (S / 4) + r.
+__host__ __device__ inline uint32_t vgroup(int g) { return (uint32_t)g * 1024u; }
+__host__ __device__ inline uint32_t sgroup(int S, int r) { return (uint32_t)vec_planes(S) * 1024u + (uint32_t)r * 256u; }
 // Byte offsets of entry k of pixel j: a per-pixel part (voff) and a
 // per-entry part (soff); the entry's address is base + soff + voff.
-__host__ __device__ inline void entry_offsets(int S, int k, uint32_t j, uint32_t pitch,
-                                              uint32_t &voff, uint32_t &soff)
+__host__ __device__ inline void entry_offsets(int S, int k, uint32_t j, uint32_t &voff,
+                                              uint32_t &soff)
 {
     const int G = vec_planes(S);
     if (k < 4 * G) {
-        voff = j * 16u + (uint32_t)(k % 4) * 4u;
-        soff = (uint32_t)(k / 4) * pitch * 16u;
+        voff = vslot(j, S) + (uint32_t)(k % 4) * 4u;
+        soff = vgroup(k / 4);
     } else {
-        voff = j * 4u;
-        soff = (uint32_t)(4 * G) * pitch * 4u + (uint32_t)(k - 4 * G) * pitch * 4u;
+        voff = sslot(j, S);
+        soff = sgroup(S, k - 4 * G);
     }
 }
 
@@ -52,7 +65,7 @@ struct FrameArgs {
     const float *state_in;  // state copy of the previous frame (layout above)
     float *state_out;       // state copy of this frame
     int32_t W, H;
-    int64_t pitch;          // pixels per state plane
+    int64_t pitch;          // pixel slots of a state copy (layout above)
     float lambda, inv_lambda, p0, var_floor;
     float alpha, inv_h2, eps;  // paper mode: Eq. 12 history weight, 1/h^2 and eps of Eq. 13
     int32_t fresh;          // 1: no history (first frame)
@@ -109,13 +122,12 @@ constexpr int kBlendR = 2;
 
 // S: state entries per pixel (state_floats(d), plus 3 history entries in
 // paper mode).
-hipError_t launch_reset(float *state, int64_t pitch, int64_t npix, int d, int S, float p0,
-                        hipStream_t st);
+hipError_t launch_reset(float *state, int64_t npix, int d, int S, float p0, hipStream_t st);
 // Copies entries k0 .. k0 + count - 1 of every pixel between a state copy
 // (layout above) and caller planes [count][npix]; to_state selects the
 // direction.
-hipError_t launch_convert(float *state, float *planes, int64_t pitch, int64_t npix, int S, int k0,
-                          int count, bool to_state, hipStream_t st);
+hipError_t launch_convert(float *state, float *planes, int64_t npix, int S, int k0, int count,
+                          bool to_state, hipStream_t st);
 hipError_t launch_step(int d, bool f16, const FrameArgs &a, TileShape ts, hipStream_t st);
 // The paper's own predictor and weight (d = 4, state with history).
 hipError_t launch_step_paper(bool f16, const FrameArgs &a, TileShape ts, hipStream_t st);

@@ -72,13 +72,16 @@ __device__ __forceinline__ void bstore(Rsrc r, uint32_t voff, uint32_t soff, flo
 typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(1))) const f4_t gcf4_t;
 typedef __attribute__((address_space(1))) f4_t gf4_t;
-__device__ __forceinline__ gcf4_t *vec_plane(const float *state, int g, uint32_t pitch)
+typedef __attribute__((address_space(1))) const char gcchar_t;
+typedef __attribute__((address_space(1))) char gchar_t;
+// The 16-byte slot at byte offsets goff (entry group, uniform) + slot (per pixel).
+__device__ __forceinline__ gcf4_t *vec_at(const float *state, uint32_t goff, uint32_t slot)
 {
-    return (gcf4_t *)(state + (size_t)g * pitch * 4u);
+    return (gcf4_t *)(((gcchar_t *)state + goff) + slot);
 }
-__device__ __forceinline__ gf4_t *vec_plane(float *state, int g, uint32_t pitch)
+__device__ __forceinline__ gf4_t *vec_at(float *state, uint32_t goff, uint32_t slot)
 {
-    return (gf4_t *)(state + (size_t)g * pitch * 4u);
+    return (gf4_t *)(((gchar_t *)state + goff) + slot);
 }
 
 // Element j of plane `plane` of an input array of planes of n values.
@@ -99,8 +102,8 @@ __device__ __forceinline__ bool finite(float v) { return __builtin_isfinite(v); 
 // the NS state entries of pixel (x, y) gathered from the previous frame's
 // state at (x, y) + v.  Returns false when the pixel has no valid source
 // (first frame, non-finite motion, source outside the image).  The vector
-// planes (four entries per 16-byte access) come first, then the scalar
-// remainder (entry_offsets).
+// groups (four entries per 16-byte access) come first, then the scalar
+// remainder.
 template <int NS>
 __device__ __forceinline__ bool gather_state(const FrameArgs &a, int x, int y, uint32_t j,
                                              uint32_t n, float (&st)[NS])
@@ -119,21 +122,20 @@ __device__ __forceinline__ bool gather_state(const FrameArgs &a, int x, int y, u
     if (!(sx >= 0.0f && sx <= (float)(a.W - 1) && sy >= 0.0f && sy <= (float)(a.H - 1)))
         return false;
     const uint32_t pitch = (uint32_t)a.pitch;
-    const uint32_t sbase = (uint32_t)(4 * G) * pitch * 4u; // first scalar plane
     const Rsrc src = array_rsrc(a.state_in, (uint32_t)NS * pitch * 4u);
     if (a.nearest) {
         const int xn = min((int)floorf(sx + 0.5f), a.W - 1);
         const int yn = min((int)floorf(sy + 0.5f), a.H - 1);
         const uint32_t i = (uint32_t)yn * (uint32_t)a.W + (uint32_t)xn;
+        const uint32_t vi = vslot(i, NS);
 #pragma unroll
         for (int g = 0; g < G; g++) {
-            const f4_t v = vec_plane(a.state_in, g, pitch)[i];
+            const f4_t v = *vec_at(a.state_in, vgroup(g), vi);
 #pragma unroll
             for (int e = 0; e < 4; e++) st[4 * g + e] = v[e];
         }
 #pragma unroll
-        for (int k = 4 * G; k < NS; k++)
-            st[k] = bload(src, i * 4u, sbase + (uint32_t)(k - 4 * G) * pitch * 4u);
+        for (int k = 4 * G; k < NS; k++) st[k] = bload(src, sslot(i, NS), sgroup(NS, k - 4 * G));
         return true;
     }
     const float fx0 = floorf(sx), fy0 = floorf(sy);
@@ -146,10 +148,12 @@ __device__ __forceinline__ bool gather_state(const FrameArgs &a, int x, int y, u
     // Bilinear in nested-lerp form (exact for a constant field).  One vector
     // plane per batch: its four taps (16 entries) are issued back to back,
     // behind a scheduling barrier, before any is consumed.
+    const uint32_t v00 = vslot(i00, NS), v10 = vslot(i10, NS), v01 = vslot(i01, NS), v11 = vslot(i11, NS);
 #pragma unroll
     for (int g = 0; g < G; g++) {
-        gcf4_t *pl = vec_plane(a.state_in, g, pitch);
-        const f4_t t00 = pl[i00], t10 = pl[i10], t01 = pl[i01], t11 = pl[i11];
+        const uint32_t go = vgroup(g);
+        const f4_t t00 = *vec_at(a.state_in, go, v00), t10 = *vec_at(a.state_in, go, v10);
+        const f4_t t01 = *vec_at(a.state_in, go, v01), t11 = *vec_at(a.state_in, go, v11);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int e = 0; e < 4; e++) {
@@ -163,11 +167,11 @@ __device__ __forceinline__ bool gather_state(const FrameArgs &a, int x, int y, u
         float t00[R], t10[R], t01[R], t11[R];
 #pragma unroll
         for (int r = 0; r < R; r++) {
-            const uint32_t so = sbase + (uint32_t)r * pitch * 4u;
-            t00[r] = bload(src, i00 * 4u, so);
-            t10[r] = bload(src, i10 * 4u, so);
-            t01[r] = bload(src, i01 * 4u, so);
-            t11[r] = bload(src, i11 * 4u, so);
+            const uint32_t so = sgroup(NS, r);
+            t00[r] = bload(src, sslot(i00, NS), so);
+            t10[r] = bload(src, sslot(i10, NS), so);
+            t01[r] = bload(src, sslot(i01, NS), so);
+            t11[r] = bload(src, sslot(i11, NS), so);
         }
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -256,14 +260,14 @@ __device__ __forceinline__ void store_pixel(const FrameArgs &a, uint32_t j, uint
     const uint32_t pitch = (uint32_t)a.pitch;
     const Rsrc dst = array_rsrc(a.state_out, (uint32_t)NS * pitch * 4u);
     const Rsrc r_out = array_rsrc(a.out, 3u * n * 4u);
+    const uint32_t vj = vslot(j, NS);
 #pragma unroll
     for (int g = 0; g < G; g++) {
         const f4_t v = {st[4 * g], st[4 * g + 1], st[4 * g + 2], st[4 * g + 3]};
-        __builtin_nontemporal_store(v, vec_plane(a.state_out, g, pitch) + j);
+        __builtin_nontemporal_store(v, vec_at(a.state_out, vgroup(g), vj));
     }
-    const uint32_t sbase = (uint32_t)(4 * G) * pitch * 4u;
 #pragma unroll
-    for (int k = 4 * G; k < NS; k++) bstore(dst, j * 4u, sbase + (uint32_t)(k - 4 * G) * pitch * 4u, st[k]);
+    for (int k = 4 * G; k < NS; k++) bstore(dst, sslot(j, NS), sgroup(NS, k - 4 * G), st[k]);
 #pragma unroll
     for (int c = 0; c < 3; c++) bstore(r_out, j * 4u, (uint32_t)c * n * 4u, out[c]);
 }
@@ -469,8 +473,8 @@ __global__ void __launch_bounds__(256) paper_step_kernel(const FrameArgs a, cons
 
 // Initial state: P = p0 * I (p0 = 1 / delta), beta = 0 (and a zero history
 // in paper mode: S = state_floats(d) + 3), every pixel.
-__global__ void __launch_bounds__(256) reset_kernel(float *state, int64_t pitch, int64_t npix,
-                                                    int d, int S, float p0)
+__global__ void __launch_bounds__(256) reset_kernel(float *state, int64_t npix, int d, int S,
+                                                    float p0)
 {
     const int np = packed_floats(d);
     const int64_t total = (int64_t)S * npix;
@@ -485,16 +489,15 @@ __global__ void __launch_bounds__(256) reset_kernel(float *state, int64_t pitch,
                 if (k == packed_index(d, i, i)) v = p0;
         }
         uint32_t voff, soff;
-        entry_offsets(S, k, j, (uint32_t)pitch, voff, soff);
+        entry_offsets(S, k, j, voff, soff);
         state[(soff + voff) / 4u] = v;
     }
 }
 
 // Entries k0 .. k0 + count - 1 of every pixel between a state copy and
 // caller planes [count][npix].
-__global__ void __launch_bounds__(256) convert_kernel(float *state, float *planes, int64_t pitch,
-                                                      int64_t npix, int S, int k0, int count,
-                                                      int to_state)
+__global__ void __launch_bounds__(256) convert_kernel(float *state, float *planes, int64_t npix,
+                                                      int S, int k0, int count, int to_state)
 {
     const int64_t total = (int64_t)count * npix;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
@@ -502,7 +505,7 @@ __global__ void __launch_bounds__(256) convert_kernel(float *state, float *plane
         const int c = (int)(e / npix);
         const uint32_t j = (uint32_t)(e - (int64_t)c * npix);
         uint32_t voff, soff;
-        entry_offsets(S, k0 + c, j, (uint32_t)pitch, voff, soff);
+        entry_offsets(S, k0 + c, j, voff, soff);
         const size_t i = (soff + voff) / 4u;
         if (to_state)
             state[i] = planes[e];
@@ -588,11 +591,11 @@ hipError_t occupancy_batched_d(bool f16, int32_t block_threads, int *blocks_per_
 }
 
 // Entries K0 .. K0 + N - 1 of pixel jj of a state copy with NS entries per
-// pixel: the vector planes that hold them are read with 128-bit loads, the
-// entries past the vector planes with 32-bit ones.
+// pixel: the vector groups that hold them are read with 128-bit loads, the
+// scalar remainder with 32-bit ones.
 template <int NS, int K0, int N>
-__device__ __forceinline__ void load_entries(const float *state, Rsrc r_state, uint32_t pitch,
-                                             uint32_t jj, float (&out)[N])
+__device__ __forceinline__ void load_entries(const float *state, Rsrc r_state, uint32_t jj,
+                                             float (&out)[N])
 {
     constexpr int G = vec_planes(NS);
     constexpr int GA = K0 / 4;
@@ -600,15 +603,14 @@ __device__ __forceinline__ void load_entries(const float *state, Rsrc r_state, u
     if constexpr (K0 < 4 * G) {
         f4_t v[GB - GA + 1];
 #pragma unroll
-        for (int q = 0; q <= GB - GA; q++) v[q] = vec_plane(state, GA + q, pitch)[jj];
+        for (int q = 0; q <= GB - GA; q++) v[q] = *vec_at(state, vgroup(GA + q), vslot(jj, NS));
 #pragma unroll
         for (int m = 0; m < N; m++)
             if (K0 + m < 4 * G) out[m] = v[(K0 + m) / 4 - GA][(K0 + m) % 4];
     }
-    const uint32_t sbase = (uint32_t)(4 * G) * pitch * 4u;
 #pragma unroll
     for (int m = 0; m < N; m++)
-        if (K0 + m >= 4 * G) out[m] = bload(r_state, jj * 4u, sbase + (uint32_t)(K0 + m - 4 * G) * pitch * 4u);
+        if (K0 + m >= 4 * G) out[m] = bload(r_state, sslot(jj, NS), sgroup(NS, K0 + m - 4 * G));
 }
 
 // Spatial blend of neighbour-model predictions (Sec. 5.3, last paragraph),
@@ -666,7 +668,7 @@ blend_kernel(const BlendArgs a)
     // entry k of pixel jj of the current state
     auto state_entry = [&](int k, uint32_t jj) {
         uint32_t voff, soff;
-        entry_offsets(NS, k, jj, pitch, voff, soff);
+        entry_offsets(NS, k, jj, voff, soff);
         return bload(r_state, voff, soff);
     };
 
@@ -808,7 +810,7 @@ blend_kernel(const BlendArgs a)
                     for (int m = 0; m < 4 * NG; m++) v[q][m] = 0.0f;
                     if (r0 + q < kBlendSlots && hj[r0 + q] >= 0) {
                         float e[D];
-                        load_entries<NS, NP + C * D, D>(st, r_state, pitch, (uint32_t)hj[r0 + q], e);
+                        load_entries<NS, NP + C * D, D>(st, r_state, (uint32_t)hj[r0 + q], e);
 #pragma unroll
                         for (int m = 0; m < D; m++) v[q][m] = e[m];
                     }
@@ -905,29 +907,28 @@ hipError_t launch_batched_d(bool f16, const BatchTable *tab, int32_t grid, int32
 
 }  // namespace
 
-hipError_t launch_reset(float *state, int64_t pitch, int64_t npix, int d, int S, float p0,
-                        hipStream_t st)
+hipError_t launch_reset(float *state, int64_t npix, int d, int S, float p0, hipStream_t st)
 {
     (void)hipGetLastError();  // report this launch's error, not an older one
     const int64_t total = (int64_t)S * npix;
     int64_t blocks = (total + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(reset_kernel, dim3((unsigned)blocks), dim3(256), 0, st, state, pitch, npix,
-                       d, S, p0);
+    hipLaunchKernelGGL(reset_kernel, dim3((unsigned)blocks), dim3(256), 0, st, state, npix, d, S,
+                       p0);
     return hipGetLastError();
 }
 
-hipError_t launch_convert(float *state, float *planes, int64_t pitch, int64_t npix, int S, int k0,
-                          int count, bool to_state, hipStream_t st)
+hipError_t launch_convert(float *state, float *planes, int64_t npix, int S, int k0, int count,
+                          bool to_state, hipStream_t st)
 {
     const int64_t total = (int64_t)count * npix;
     if (total <= 0) return hipSuccess;
     int64_t blocks = (total + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     (void)hipGetLastError();
-    hipLaunchKernelGGL(convert_kernel, dim3((unsigned)blocks), dim3(256), 0, st, state, planes, pitch,
-                       npix, S, k0, count, to_state ? 1 : 0);
+    hipLaunchKernelGGL(convert_kernel, dim3((unsigned)blocks), dim3(256), 0, st, state, planes, npix,
+                       S, k0, count, to_state ? 1 : 0);
     return hipGetLastError();
 }
 
