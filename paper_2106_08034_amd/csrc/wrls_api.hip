@@ -388,12 +388,12 @@ wrls_status wrls_get_state(const wrls_stream *s, float *P_packed, float *beta)
     const int64_t n = (int64_t)s->prm.width * s->prm.height;
     hipError_t e;
     if (P_packed) {
-        e = wrls::launch_convert(s->state[s->cur], P_packed, n, S, 0, wrls::packed_floats(d),
+        e = wrls::launch_convert(s->state[s->cur], P_packed, n, d, S, 0, wrls::packed_floats(d),
                                  false, s->st);
         if (e != hipSuccess) return hip_fail(e, "state export (P)");
     }
     if (beta) {
-        e = wrls::launch_convert(s->state[s->cur], beta, n, S, wrls::packed_floats(d), 3 * d,
+        e = wrls::launch_convert(s->state[s->cur], beta, n, d, S, wrls::packed_floats(d), 3 * d,
                                  false, s->st);
         if (e != hipSuccess) return hip_fail(e, "state export (beta)");
     }
@@ -410,9 +410,9 @@ wrls_status wrls_set_state(wrls_stream *s, const float *P_packed, const float *b
     const int S = stream_state_floats(&s->prm);
     const int64_t n = (int64_t)s->prm.width * s->prm.height;
     hipError_t e = wrls::launch_convert(s->state[s->cur], const_cast<float *>(P_packed), n,
-                                        S, 0, wrls::packed_floats(d), true, s->st);
+                                        d, S, 0, wrls::packed_floats(d), true, s->st);
     if (e != hipSuccess) return hip_fail(e, "state import (P)");
-    e = wrls::launch_convert(s->state[s->cur], const_cast<float *>(beta), n, S,
+    e = wrls::launch_convert(s->state[s->cur], const_cast<float *>(beta), n, d, S,
                              wrls::packed_floats(d), 3 * d, true, s->st);
     if (e != hipSuccess) return hip_fail(e, "state import (beta)");
     s->frames = frames;
@@ -697,7 +697,8 @@ wrls_status wrls_get_history(const wrls_stream *s, float *z)
     if (s->prm.weight_mode != WRLS_W_PAPER) return fail(WRLS_EINVAL, "the stream has no history");
     if (!z) return fail(WRLS_EINVAL, "z is NULL");
     const int64_t n = (int64_t)s->prm.width * s->prm.height;
-    hipError_t e = wrls::launch_convert(s->state[s->cur], z, n, stream_state_floats(&s->prm),
+    hipError_t e = wrls::launch_convert(s->state[s->cur], z, n, s->prm.d,
+                                        stream_state_floats(&s->prm),
                                         wrls::state_floats(s->prm.d), 3, false, s->st);
     if (e != hipSuccess) return hip_fail(e, "history export");
     return WRLS_OK;
@@ -709,9 +710,9 @@ wrls_status wrls_set_history(wrls_stream *s, const float *z)
     if (s->prm.weight_mode != WRLS_W_PAPER) return fail(WRLS_EINVAL, "the stream has no history");
     if (!z) return fail(WRLS_EINVAL, "z is NULL");
     const int64_t n = (int64_t)s->prm.width * s->prm.height;
-    hipError_t e = wrls::launch_convert(s->state[s->cur], const_cast<float *>(z), n,
-                                        stream_state_floats(&s->prm), wrls::state_floats(s->prm.d), 3,
-                                        true, s->st);
+    hipError_t e = wrls::launch_convert(s->state[s->cur], const_cast<float *>(z), n, s->prm.d,
+                                        stream_state_floats(&s->prm),
+                                        wrls::state_floats(s->prm.d), 3, true, s->st);
     if (e != hipSuccess) return hip_fail(e, "history import");
     return WRLS_OK;
 }

@@ -40,12 +40,27 @@ __host__ __device__ inline uint32_t sslot(uint32_t j, int S) { return (j >> 6) *
 // 4 * (S / 4) + r.
 __host__ __device__ inline uint32_t vgroup(int g) { return (uint32_t)g * 1024u; }
 __host__ __device__ inline uint32_t sgroup(int S, int r) { return (uint32_t)vec_planes(S) * 1024u + (uint32_t)r * 256u; }
-// Byte offsets of entry k of pixel j: a per-pixel part (voff) and a
-// per-entry part (soff); the entry's address is base + soff + voff.
-__host__ __device__ inline void entry_offsets(int S, int k, uint32_t j, uint32_t &voff,
-                                              uint32_t &soff)
+// Order of a pixel's entries in the state: beta (3 rows of d, the colour
+// channel's coefficients contiguous), then the packed P, then the paper-mode
+// history.  With beta first, channel c starts at entry c * d: at d = 4 and 8
+// every channel starts on a 16-byte vector, so the spatial blend reads a
+// channel's coefficients with the fewest vector loads.  The export and import
+// order (wrls_get_state / wrls_set_state) is P, then beta, then the history.
+__host__ __device__ constexpr int beta_entry0(int) { return 0; }
+__host__ __device__ constexpr int p_entry0(int d) { return 3 * d; }
+// Position in the state of export-order entry k.
+__host__ __device__ inline int state_entry_index(int d, int k)
+{
+    const int np = packed_floats(d);
+    return k < np ? p_entry0(d) + k : (k < np + 3 * d ? beta_entry0(d) + (k - np) : k);
+}
+// Byte offsets of export-order entry k of pixel j: a per-pixel part (voff)
+// and a per-entry part (soff); the entry's address is base + soff + voff.
+__host__ __device__ inline void entry_offsets(int S, int d, int k_export, uint32_t j,
+                                              uint32_t &voff, uint32_t &soff)
 {
     const int G = vec_planes(S);
+    const int k = state_entry_index(d, k_export);
     if (k < 4 * G) {
         voff = vslot(j, S) + (uint32_t)(k % 4) * 4u;
         soff = vgroup(k / 4);
@@ -123,11 +138,11 @@ constexpr int kBlendR = 2;
 // S: state entries per pixel (state_floats(d), plus 3 history entries in
 // paper mode).
 hipError_t launch_reset(float *state, int64_t npix, int d, int S, float p0, hipStream_t st);
-// Copies entries k0 .. k0 + count - 1 of every pixel between a state copy
-// (layout above) and caller planes [count][npix]; to_state selects the
-// direction.
-hipError_t launch_convert(float *state, float *planes, int64_t npix, int S, int k0, int count,
-                          bool to_state, hipStream_t st);
+// Copies export-order entries k0 .. k0 + count - 1 of every pixel between a
+// state copy (layout above) and caller planes [count][npix]; to_state
+// selects the direction.
+hipError_t launch_convert(float *state, float *planes, int64_t npix, int d, int S, int k0,
+                          int count, bool to_state, hipStream_t st);
 hipError_t launch_step(int d, bool f16, const FrameArgs &a, TileShape ts, hipStream_t st);
 // The paper's own predictor and weight (d = 4, state with history).
 hipError_t launch_step_paper(bool f16, const FrameArgs &a, TileShape ts, hipStream_t st);

@@ -273,11 +273,11 @@ __device__ __forceinline__ void store_pixel(const FrameArgs &a, uint32_t j, uint
 }
 
 // The per-pixel update with supplied features.  D: predictor length; InT:
-// colour/feature type.  State: packed P (D(D+1)/2 entries), then beta.
+// colour/feature type.  State: beta (3 rows of D), then packed P
+// (D(D+1)/2 entries).
 template <int D, typename InT>
 __device__ __forceinline__ void update_pixel(const FrameArgs &a, int x, int y)
 {
-    constexpr int NP = packed_floats(D);
     constexpr int NS = state_floats(D);
     const uint32_t n = (uint32_t)a.W * (uint32_t)a.H;
     const uint32_t j = (uint32_t)y * (uint32_t)a.W + (uint32_t)x;
@@ -313,15 +313,15 @@ __device__ __forceinline__ void update_pixel(const FrameArgs &a, int x, int y)
     }
 
     float st[NS];
-    if (!gather_state<NS>(a, x, y, j, n, st)) init_model<D>(a.p0, st, st + NP);
+    if (!gather_state<NS>(a, x, y, j, n, st)) init_model<D>(a.p0, st + p_entry0(D), st + beta_entry0(D));
     float out[3];
-    rls_update<D>(st, st + NP, p, yc, w, ok, a.lambda, a.inv_lambda, out);
+    rls_update<D>(st + p_entry0(D), st + beta_entry0(D), p, yc, w, ok, a.lambda, a.inv_lambda, out);
     store_pixel<NS>(a, j, n, st, out);
 }
 
 // The per-pixel update with the paper's own predictor and weight (Sec. 5.3):
 // p = [1, z] with the temporal feature z of Eq. 12 and the weight of Eq. 13.
-// State: packed P (10), beta (12), then the history z (3).
+// State: beta (12), packed P (10), then the history z (3).
 // col: the frame's colour over the workgroup's tile and a 1-pixel halo,
 // staged in LDS as 3 planes of nc floats (NaN outside the image), rows of
 // rw floats; c0: this pixel's position in a plane.
@@ -330,7 +330,6 @@ __device__ __forceinline__ void update_pixel_paper(const FrameArgs &a, int x, in
                                                    const float *col, int nc, int rw, int c0)
 {
     constexpr int D = 4;
-    constexpr int NP = packed_floats(D);
     constexpr int NM = state_floats(D);  // model entries; the history follows
     constexpr int NS = NM + 3;
     const uint32_t n = (uint32_t)a.W * (uint32_t)a.H;
@@ -347,7 +346,7 @@ __device__ __forceinline__ void update_pixel_paper(const FrameArgs &a, int x, in
 
     float st[NS];
     const bool have = gather_state<NS>(a, x, y, j, n, st);
-    if (!have) init_model<D>(a.p0, st, st + NP);
+    if (!have) init_model<D>(a.p0, st + p_entry0(D), st + beta_entry0(D));
     float z[3];
     if (ok) {
         // Eq. 12: history clamped to the current colour's range over the 3x3
@@ -396,7 +395,7 @@ __device__ __forceinline__ void update_pixel_paper(const FrameArgs &a, int x, in
     }
     const float p[D] = {1.0f, z[0], z[1], z[2]};
     float out[3];
-    rls_update<D>(st, st + NP, p, yc, w, ok, a.lambda, a.inv_lambda, out);
+    rls_update<D>(st + p_entry0(D), st + beta_entry0(D), p, yc, w, ok, a.lambda, a.inv_lambda, out);
 #pragma unroll
     for (int c = 0; c < 3; c++) st[NM + c] = z[c];
     store_pixel<NS>(a, j, n, st, out);
@@ -489,7 +488,7 @@ __global__ void __launch_bounds__(256) reset_kernel(float *state, int64_t npix, 
                 if (k == packed_index(d, i, i)) v = p0;
         }
         uint32_t voff, soff;
-        entry_offsets(S, k, j, voff, soff);
+        entry_offsets(S, d, k, j, voff, soff);
         state[(soff + voff) / 4u] = v;
     }
 }
@@ -497,7 +496,7 @@ __global__ void __launch_bounds__(256) reset_kernel(float *state, int64_t npix, 
 // Entries k0 .. k0 + count - 1 of every pixel between a state copy and
 // caller planes [count][npix].
 __global__ void __launch_bounds__(256) convert_kernel(float *state, float *planes, int64_t npix,
-                                                      int S, int k0, int count, int to_state)
+                                                      int d, int S, int k0, int count, int to_state)
 {
     const int64_t total = (int64_t)count * npix;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
@@ -505,7 +504,7 @@ __global__ void __launch_bounds__(256) convert_kernel(float *state, float *plane
         const int c = (int)(e / npix);
         const uint32_t j = (uint32_t)(e - (int64_t)c * npix);
         uint32_t voff, soff;
-        entry_offsets(S, k0 + c, j, voff, soff);
+        entry_offsets(S, d, k0 + c, j, voff, soff);
         const size_t i = (soff + voff) / 4u;
         if (to_state)
             state[i] = planes[e];
@@ -649,7 +648,6 @@ __global__ void __launch_bounds__(kBlendThreads) __attribute__((amdgpu_waves_per
 blend_kernel(const BlendArgs a)
 {
     constexpr int RPT = kBlendRPT;
-    constexpr int NP = packed_floats(D);
     constexpr int NS = state_floats(D) + (PAPER ? 3 : 0);
     constexpr int NG = (D + 3) / 4;  // groups of four beta planes
     __shared__ float4 s_guide[kBlendRN];
@@ -668,7 +666,7 @@ blend_kernel(const BlendArgs a)
     // entry k of pixel jj of the current state
     auto state_entry = [&](int k, uint32_t jj) {
         uint32_t voff, soff;
-        entry_offsets(NS, k, jj, voff, soff);
+        entry_offsets(NS, D, k, jj, voff, soff);
         return bload(r_state, voff, soff);
     };
 
@@ -810,7 +808,7 @@ blend_kernel(const BlendArgs a)
                     for (int m = 0; m < 4 * NG; m++) v[q][m] = 0.0f;
                     if (r0 + q < kBlendSlots && hj[r0 + q] >= 0) {
                         float e[D];
-                        load_entries<NS, NP + C * D, D>(st, r_state, (uint32_t)hj[r0 + q], e);
+                        load_entries<NS, beta_entry0(D) + C * D, D>(st, r_state, (uint32_t)hj[r0 + q], e);
 #pragma unroll
                         for (int m = 0; m < D; m++) v[q][m] = e[m];
                     }
@@ -919,8 +917,8 @@ hipError_t launch_reset(float *state, int64_t npix, int d, int S, float p0, hipS
     return hipGetLastError();
 }
 
-hipError_t launch_convert(float *state, float *planes, int64_t npix, int S, int k0, int count,
-                          bool to_state, hipStream_t st)
+hipError_t launch_convert(float *state, float *planes, int64_t npix, int d, int S, int k0,
+                          int count, bool to_state, hipStream_t st)
 {
     const int64_t total = (int64_t)count * npix;
     if (total <= 0) return hipSuccess;
@@ -928,7 +926,7 @@ hipError_t launch_convert(float *state, float *planes, int64_t npix, int S, int 
     if (blocks > 65536) blocks = 65536;
     (void)hipGetLastError();
     hipLaunchKernelGGL(convert_kernel, dim3((unsigned)blocks), dim3(256), 0, st, state, planes, npix,
-                       S, k0, count, to_state ? 1 : 0);
+                       d, S, k0, count, to_state ? 1 : 0);
     return hipGetLastError();
 }
 
