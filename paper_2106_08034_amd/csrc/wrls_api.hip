@@ -53,7 +53,15 @@ int64_t plane_pitch(const wrls_params *p)
     return q * a;
 }
 
-wrls::TileShape default_tile() { return wrls::TileShape{7, 128, 0}; }
+// Default launch shapes: 128 x 1 for supplied features; 64 x 2 in paper
+// mode, whose kernel stages a colour halo per tile (fewer halo rows per
+// pixel).
+constexpr wrls::TileShape kDefaultTile{7, 128, 0};
+constexpr wrls::TileShape kDefaultPaperTile{6, 128, 0};
+wrls::TileShape default_tile(const wrls_params *p)
+{
+    return p->weight_mode == WRLS_W_PAPER ? kDefaultPaperTile : kDefaultTile;
+}
 
 bool aligned(const void *ptr, size_t bytes) { return ((uintptr_t)ptr % bytes) == 0; }
 
@@ -163,7 +171,7 @@ wrls_status init_stream(const wrls_params *p, void *hip_stream, void *mem, bool 
     s->pitch = plane_pitch(p);
     s->cur = 0;
     s->frames = 0;
-    s->tile = default_tile();
+    s->tile = default_tile(p);
     s->alloc = mem;
     s->owns_alloc = owns;
     const size_t one = (size_t)stream_state_floats(p) * (size_t)s->pitch;
@@ -542,7 +550,7 @@ wrls_status wrls_batch_create(int32_t max_streams, int32_t d, int32_t in_dtype, 
     b->max_streams = max_streams;
     b->d = d;
     b->in_dtype = in_dtype;
-    b->tile = default_tile();
+    b->tile = kDefaultTile;
     b->use_graph = true;
     b->blocks_per_cu = 0;
     hipError_t e = hipSuccess;

@@ -325,27 +325,23 @@ __device__ __forceinline__ void update_pixel(const FrameArgs &a, int x, int y)
 // col: the frame's colour over the workgroup's tile and a 1-pixel halo,
 // staged in LDS as 3 planes of nc floats (NaN outside the image), rows of
 // rw floats; c0: this pixel's position in a plane.
-template <typename InT>
+// st / have: the pixel's reprojected state and whether it has a source
+// (gather_state).
+constexpr int kPaperNS = state_floats(4) + 3;
 __device__ __forceinline__ void update_pixel_paper(const FrameArgs &a, int x, int y,
+                                                   float (&st)[kPaperNS], bool have,
                                                    const float *col, int nc, int rw, int c0)
 {
     constexpr int D = 4;
     constexpr int NM = state_floats(D);  // model entries; the history follows
-    constexpr int NS = NM + 3;
+    constexpr int NS = kPaperNS;
     const uint32_t n = (uint32_t)a.W * (uint32_t)a.H;
     const uint32_t j = (uint32_t)y * (uint32_t)a.W + (uint32_t)x;
-    const InT *tag = nullptr;
-    const Rsrc r_color = array_rsrc(a.color, 3u * n * (uint32_t)sizeof(InT));
-
-    (void)r_color;
-    (void)tag;
     float yc[3];
 #pragma unroll
     for (int c = 0; c < 3; c++) yc[c] = col[c * nc + c0];
     const bool ok = finite(yc[0]) && finite(yc[1]) && finite(yc[2]);
 
-    float st[NS];
-    const bool have = gather_state<NS>(a, x, y, j, n, st);
     if (!have) init_model<D>(a.p0, st + p_entry0(D), st + beta_entry0(D));
     float z[3];
     if (ok) {
@@ -441,7 +437,12 @@ __global__ void __launch_bounds__(256) step_kernel(const FrameArgs a, const Tile
 
 // The tile's colour and a 1-pixel halo are staged in LDS once per
 // workgroup (dynamic size 3 (tw + 2) (th + 2) floats): the 3x3 clamp bounds
-// then cost LDS reads instead of 27 global loads per pixel.
+// then cost LDS reads instead of 27 global loads per pixel.  The colour
+// loads are issued first and the state gather next, so that both are in
+// flight together before the barrier.  A thread stages at most
+// kPaperSlots halo pixels: (tw + 2)(th + 2) <= 3 (T + 2) <= 4 T for the
+// accepted shapes (T = tw th >= 64 threads).
+constexpr int kPaperSlots = 4;
 template <typename InT>
 __global__ void __launch_bounds__(256) paper_step_kernel(const FrameArgs a, const TileShape ts)
 {
@@ -456,18 +457,31 @@ __global__ void __launch_bounds__(256) paper_step_kernel(const FrameArgs a, cons
     const uint32_t n = (uint32_t)a.W * (uint32_t)a.H;
     const InT *tag = nullptr;
     const Rsrc r_color = array_rsrc(a.color, 3u * n * (uint32_t)sizeof(InT));
-    for (int sl = (int)threadIdx.x; sl < nc; sl += ts.block_threads) {
+    float cv[kPaperSlots][3];
+#pragma unroll
+    for (int q = 0; q < kPaperSlots; q++) {
+        const int sl = (int)threadIdx.x + q * ts.block_threads;
         const int hy = sl / rw, hx = sl - hy * rw;
         const int gx = x0 - 1 + hx, gy = y0 - 1 + hy;
-        const bool in = gx >= 0 && gx < a.W && gy >= 0 && gy < a.H;
+        const bool in = sl < nc && gx >= 0 && gx < a.W && gy >= 0 && gy < a.H;
         const uint32_t jn = in ? (uint32_t)gy * (uint32_t)a.W + (uint32_t)gx : 0u;
 #pragma unroll
-        for (int c = 0; c < 3; c++) s_col[c * nc + sl] = in ? load_in(r_color, tag, n, c, jn) : __builtin_nanf("");
+        for (int c = 0; c < 3; c++) cv[q][c] = in ? load_in(r_color, tag, n, c, jn) : __builtin_nanf("");
+    }
+    const int x = x0 + lx, y = y0 + ly;
+    const bool mine = x < a.W && y < a.H;
+    float st[kPaperNS];
+    const bool have = mine && gather_state<kPaperNS>(a, x, y, (uint32_t)y * (uint32_t)a.W + (uint32_t)x, n, st);
+#pragma unroll
+    for (int q = 0; q < kPaperSlots; q++) {
+        const int sl = (int)threadIdx.x + q * ts.block_threads;
+        if (sl < nc)
+#pragma unroll
+            for (int c = 0; c < 3; c++) s_col[c * nc + sl] = cv[q][c];
     }
     __syncthreads();
-    const int x = x0 + lx, y = y0 + ly;
-    if (x >= a.W || y >= a.H) return;  // after the barrier
-    update_pixel_paper<InT>(a, x, y, s_col, nc, rw, (ly + 1) * rw + lx + 1);
+    if (!mine) return;  // after the barrier
+    update_pixel_paper(a, x, y, st, have, s_col, nc, rw, (ly + 1) * rw + lx + 1);
 }
 
 // Initial state: P = p0 * I (p0 = 1 / delta), beta = 0 (and a zero history
@@ -943,6 +957,7 @@ hipError_t launch_step_paper(bool f16, const FrameArgs &a, TileShape ts, hipStre
     const int strip_w = ts.strip_w <= 0 ? tiles_x : ts.strip_w;
     b.strip_w = strip_w > tiles_x ? tiles_x : strip_w;
     const dim3 grid((unsigned)(tiles_x * tiles_y)), block((unsigned)ts.block_threads);
+    if (th < 1 || (tw + 2) * (th + 2) > kPaperSlots * ts.block_threads) return hipErrorInvalidValue;
     const size_t lds = 3u * (size_t)(tw + 2) * (size_t)(th + 2) * sizeof(float);
     if (f16)
         hipLaunchKernelGGL((paper_step_kernel<_Float16>), grid, block, lds, st, b, ts);

@@ -179,3 +179,36 @@ def test_batch_rejects_paper_streams():
     with pytest.raises(wrls.WrlsError) as ei:
         b.step([s], [(c, None, None, None)])
     assert ei.value.status == wrls.WRLS_EUNSUPPORTED
+
+
+def test_paper_every_launch_shape_bitwise():
+    """The paper kernel stages a colour halo per tile, so its indexing depends
+    on the launch shape: every accepted shape (extremes included: 1-pixel-wide
+    tiles, 256 x 1, 16 x 16) must give the default shape's outputs and state
+    bitwise, and the default shape matches the oracle."""
+    import torch
+    from paper_2106_08034_amd import wrls
+    wl = synth.c2(width=133, height=41, frames=4)
+    src = synth.FrameSource(wl)
+    frames = [src.next() for _ in range(wl.frames)]
+    pair = Pair(wl.width, wl.height, 4, weight_mode="paper")
+    assert pair.gpu.tile == (6, 128, 0)  # paper-mode default: 64 x 2
+    outs = []
+    for f in frames:
+        out, ref, e = pair.step(f.color, None, None, f.motion)
+        assert e <= G1_TOL
+        outs.append(out)
+    P0, B0 = pair.gpu.get_state()
+    z0 = pair.gpu.get_history()
+    shapes = [(0, 64), (1, 64), (6, 64), (8, 256), (4, 256), (0, 256), (7, 128), (2, 128)]
+    for tw, bt in shapes:
+        log("case paper shape %dx%d" % (1 << tw, bt >> tw))
+        s = wrls.Stream(wl.width, wl.height, 4, weight_mode="paper")
+        s.set_tile(tw, bt, 0)
+        for t, f in enumerate(frames):
+            got = s.step(to_dev(f.color), None, None, to_dev(f.motion))
+            assert np.array_equal(got.cpu().numpy(), outs[t]), ((tw, bt), t)
+        P, B = s.get_state()
+        assert torch.equal(P, P0) and torch.equal(B, B0) and torch.equal(s.get_history(), z0), (tw, bt)
+        s.close()
+    torch.cuda.synchronize()
