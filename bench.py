@@ -52,6 +52,20 @@ def blend_bytes_per_pixel(d: int, in_bytes: int, paper: bool = False) -> int:
     return 3 * d * 4 + pred + 12 + 12
 
 
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector peak (packed FMA); non-packed: 78.6
+
+
+def blend_flop_per_pixel(d: int) -> int:
+    """Arithmetic of the 5x5 spatial blend per output pixel, counting an FMA
+    as 2 flop and exp as 1: for each of the 24 non-centre neighbours the
+    bilateral weight (3 colour differences, the squared distance as 1
+    multiply and 2 FMAs, the exponent as 1 FMA, exp, the running sum:
+    12 flop); for each of the 25 neighbours, 3 channels times d FMAs of the
+    weighted coefficient sum; then per channel the dot product with p (d - 1
+    FMAs, p_0 = 1) and the normalisation (3 multiplies, 1 division)."""
+    return 24 * 12 + 25 * 3 * d * 2 + 3 * (d - 1) * 2 + 4
+
+
 def kernel_source_hash() -> str:
     """Identifies the code that shapes a launch's memory traffic: the kernels,
     the internal header whose constants they compile with, and the host side
@@ -552,6 +566,13 @@ def main():
         "frac": round(bbpp * npix / blend_s / 1e9 / HBM_PEAK_GBS, 4),
         "traffic": load_traffic(args.workload, "blend"),
         "step_plus_blend_mpix_per_s": round(npix / (avg_launch_s + blend_s) / 1e6, 1)}
+    # the blend is bound by vector ALU work, not HBM: its arithmetic rate too
+    bflop = blend_flop_per_pixel(d_model)
+    alu_tflops = bflop * npix / blend_s / 1e12
+    line["spatial_blend"]["alu"] = {
+        "bound": "alu", "flop_per_pixel": bflop, "achieved": round(alu_tflops, 2),
+        "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+        "frac": round(alu_tflops / FP32_VECTOR_PEAK_TFLOPS, 4)}
     stream.close()
     if not args.no_serving and args.workload == "c2":
         del dev_frames

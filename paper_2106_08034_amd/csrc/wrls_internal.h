@@ -147,7 +147,7 @@ hipError_t launch_step(int d, bool f16, const FrameArgs &a, TileShape ts, hipStr
 // The paper's own predictor and weight (d = 4, state with history).
 hipError_t launch_step_paper(bool f16, const FrameArgs &a, TileShape ts, hipStream_t st);
 // The 5x5 spatial blend of neighbour-model predictions; paper: p = [1, z]
-// from the state's history planes (d = 4).
+// from the state's history entries (d = 4).
 hipError_t launch_blend(int d, bool f16, bool paper, const BlendArgs &a, hipStream_t st);
 // One persistent launch of `grid` workgroups of tab->tile.block_threads
 // threads over every tile of every frame in the device table `tab`.

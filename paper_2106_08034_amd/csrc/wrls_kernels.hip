@@ -9,12 +9,13 @@
 //   prediction (Eq. 6); store the new state and the output.
 // The work is a batch of tiny independent d x d problems: about 1.7 flop per
 // byte of HBM traffic, far below the MI355X ridge, so the kernel is built
-// around memory traffic, not matrix cores.  State is stored as planes (one
-// plane per state entry, padded to 256 B) so that a 64-lane wavefront on a
-// row segment reads and writes 256 contiguous bytes per entry; the bilinear
-// gather of a uniformly moving row is then two such runs per tap row, which
-// the L1/L2 caches merge.  Tiles are handed to the eight XCDs in contiguous
-// ranges so neighbouring tiles, which share source rows, meet in one L2.
+// around memory traffic, not matrix cores.  State is stored in chunks of 64
+// pixels, four entries of a pixel per 16-byte vector (wrls_internal.h), so
+// that a 64-lane wavefront on a row segment moves 1 KiB of contiguous bytes
+// per vector group; the bilinear gather of a uniformly moving row is then at
+// most two such runs per tap row, which the L1/L2 caches merge.  Tiles are
+// handed to the eight XCDs in contiguous ranges so neighbouring tiles, which
+// share source rows, meet in one L2.
 #include "wrls_internal.h"
 
 namespace wrls {
@@ -39,11 +40,12 @@ __device__ __forceinline__ int xcd_tile(int b, int nblocks)
     return start + idx;
 }
 
-// Every access goes through a raw buffer descriptor of one whole array
-// (built once, in scalar registers) with the plane offset as the scalar
-// offset and a 32-bit per-lane byte offset.  The address needs no per-lane
-// 64-bit math, and an access past the array reads 0 / is dropped instead of
-// faulting.  The host guarantees every array is below 4 GiB.
+// Inputs, outputs and the scalar state entries go through a raw buffer
+// descriptor of one whole array (built once, in scalar registers) with the
+// plane or group offset as the scalar offset and a 32-bit per-lane byte
+// offset.  The address needs no per-lane 64-bit math, and an access past the
+// array reads 0 / is dropped instead of faulting.  The host guarantees every
+// array is below 4 GiB.
 using Rsrc = __amdgpu_buffer_rsrc_t;
 constexpr int kRawBufferWord3 = 0x00020000;  // gfx9-family raw buffer, 32-bit data
 
@@ -66,8 +68,8 @@ __device__ __forceinline__ void bstore(Rsrc r, uint32_t voff, uint32_t soff, flo
 // loads and non-temporal stores of a 4-float vector: global_load_dwordx4 /
 // global_store_dwordx4.  (This compiler lowers the 128-bit raw-buffer-load
 // builtin to a single 32-bit load, so the buffer path is not used for them.)
-// Vector plane g of a state copy starts at float g * pitch * 4.
-// The pointers are marked global: state pointers read from a device table
+// The address is the array base plus a uniform group offset plus a 32-bit
+// per-pixel slot offset (vgroup, vslot).  The pointers are marked global: state pointers read from a device table
 // (batched steps) would otherwise compile to flat accesses.
 typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(1))) const f4_t gcf4_t;
@@ -153,7 +155,7 @@ __device__ __forceinline__ bool gather_state(const FrameArgs &a, int x, int y, f
     const uint32_t i00 = (uint32_t)y0 * W + (uint32_t)x0, i10 = (uint32_t)y0 * W + (uint32_t)x1;
     const uint32_t i01 = (uint32_t)y1 * W + (uint32_t)x0, i11 = (uint32_t)y1 * W + (uint32_t)x1;
     // Bilinear in nested-lerp form (exact for a constant field).  One vector
-    // plane per batch: its four taps (16 entries) are issued back to back,
+    // group per batch: its four taps (16 entries) are issued back to back,
     // behind a scheduling barrier, before any is consumed.
     const uint32_t v00 = vslot(i00, NS), v10 = vslot(i10, NS), v01 = vslot(i01, NS), v11 = vslot(i11, NS);
 #pragma unroll
@@ -257,7 +259,7 @@ __device__ __forceinline__ void rls_update(float *P, float *B, const float (&p)[
     }
 }
 
-// Stores the NS state entries of pixel j (vector planes, then the scalar
+// Stores the NS state entries of pixel j (vector groups, then the scalar
 // remainder) and its output.
 template <int NS>
 __device__ __forceinline__ void store_pixel(const FrameArgs &a, uint32_t j, uint32_t n,
@@ -646,15 +648,15 @@ __device__ __forceinline__ void load_entries(const float *state, Rsrc r_state, u
 //   w_ik = exp(-|x_k - x_i|^2 / (2 sigma_s^2) - |yhat_k - yhat_i|^2 / (2 sigma_r^2)),
 // yhat being the step's output.  Since every prediction uses p_i, the sum is
 // p_i (sum_k w_ik beta_k^T) / sum_k w_ik: per channel a weighted 5x5 stencil
-// over the D beta planes, then one dot product.
+// over the D beta entries, then one dot product.
 //
 // One workgroup per 64 x kBlendTH tile; each thread computes RPT vertically
 // adjacent pixels.  The guide of the tile and its 2-pixel halo is staged in
 // LDS and every thread keeps its 25 RPT weights in registers; then, one
-// channel at a time, the channel's beta planes of the halo are staged in
+// channel at a time, the channel's beta entries of the halo are staged in
 // LDS and accumulated.  A thread reads each halo row once for all RPT of
 // its pixels (LDS traffic per pixel: 5 (RPT + 4) / RPT reads instead of 25).
-// LDS holds the planes in groups of four, one 16-byte vector per halo pixel
+// LDS holds the entries in groups of four, one 16-byte vector per halo pixel
 // and group (the guide likewise, padded): a neighbour costs one 128-bit read
 // per group, every read is an immediate offset from one base address (no
 // per-read address arithmetic on the vector ALU, which bounds this kernel),
@@ -676,7 +678,7 @@ blend_kernel(const BlendArgs a)
 {
     constexpr int RPT = kBlendRPT;
     constexpr int NS = state_floats(D) + (PAPER ? 3 : 0);
-    constexpr int NG = (D + 3) / 4;  // groups of four beta planes
+    constexpr int NG = (D + 3) / 4;  // groups of four beta entries
     __shared__ float4 s_guide[kBlendRN];
     __shared__ float4 s_beta[NG][kBlendRN];
 
