@@ -34,12 +34,21 @@ __host__ __device__ constexpr int packed_index(int d, int i, int m)
 __host__ __device__ constexpr int vec_planes(int S) { return S / 4; }
 // Byte offset of pixel j's 16-byte slot (vector entries) and 4-byte slot
 // (scalar entries) relative to the start of an entry group of its chunk.
-__host__ __device__ inline uint32_t vslot(uint32_t j, int S) { return (j >> 6) * (uint32_t)S * 256u + (j & 63u) * 16u; }
-__host__ __device__ inline uint32_t sslot(uint32_t j, int S) { return (j >> 6) * (uint32_t)S * 256u + (j & 63u) * 4u; }
+__host__ __device__ inline uint32_t vslot(uint32_t j, int S)
+{
+    return (j >> 6) * (uint32_t)S * 256u + (j & 63u) * 16u;
+}
+__host__ __device__ inline uint32_t sslot(uint32_t j, int S)
+{
+    return (j >> 6) * (uint32_t)S * 256u + (j & 63u) * 4u;
+}
 // Byte offset, within a chunk, of vector group g and of scalar entry
 // 4 * (S / 4) + r.
 __host__ __device__ inline uint32_t vgroup(int g) { return (uint32_t)g * 1024u; }
-__host__ __device__ inline uint32_t sgroup(int S, int r) { return (uint32_t)vec_planes(S) * 1024u + (uint32_t)r * 256u; }
+__host__ __device__ inline uint32_t sgroup(int S, int r)
+{
+    return (uint32_t)vec_planes(S) * 1024u + (uint32_t)r * 256u;
+}
 // Order of a pixel's entries in the state: beta (3 rows of d, the colour
 // channel's coefficients contiguous), then the packed P, then the paper-mode
 // history.  With beta first, channel c starts at entry c * d: at d = 4 and 8

@@ -69,8 +69,9 @@ __device__ __forceinline__ void bstore(Rsrc r, uint32_t voff, uint32_t soff, flo
 // global_store_dwordx4.  (This compiler lowers the 128-bit raw-buffer-load
 // builtin to a single 32-bit load, so the buffer path is not used for them.)
 // The address is the array base plus a uniform group offset plus a 32-bit
-// per-pixel slot offset (vgroup, vslot).  The pointers are marked global: state pointers read from a device table
-// (batched steps) would otherwise compile to flat accesses.
+// per-pixel slot offset (vgroup, vslot).  The pointers are marked global:
+// state pointers read from a device table (batched steps) would otherwise
+// compile to flat accesses.
 typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(1))) const f4_t gcf4_t;
 typedef __attribute__((address_space(1))) f4_t gf4_t;
@@ -100,12 +101,6 @@ __device__ __forceinline__ float load_in(Rsrc r, const _Float16 *, uint32_t n, i
 
 __device__ __forceinline__ bool finite(float v) { return __builtin_isfinite(v); }
 
-// Reprojection (Sec. 5.3, Table 2: pi(v_j) = j + v_j in the previous frame):
-// the NS state entries of pixel (x, y) gathered from the previous frame's
-// state at (x, y) + v, v = (vx, vy).  Returns false when the pixel has no valid source
-// (first frame, non-finite motion, source outside the image).  The vector
-// groups (four entries per 16-byte access) come first, then the scalar
-// remainder.
 // The motion vector of pixel j (zero without a motion array); loaded ahead of
 // the other inputs, since the gather's addresses wait on it.
 __device__ __forceinline__ void load_motion(const FrameArgs &a, uint32_t j, uint32_t n, float &vx,
@@ -119,6 +114,12 @@ __device__ __forceinline__ void load_motion(const FrameArgs &a, uint32_t j, uint
         vy = bload(r_mot, j * 4u, n * 4u);
     }
 }
+// Reprojection (Sec. 5.3, Table 2: pi(v_j) = j + v_j in the previous frame):
+// the NS state entries of pixel (x, y) gathered from the previous frame's
+// state at (x, y) + v, v = (vx, vy).  Returns false when the pixel has no
+// valid source (first frame, non-finite motion, source outside the image).
+// The vector groups (four entries per 16-byte access) come first, then the
+// scalar remainder.
 template <int NS>
 __device__ __forceinline__ bool gather_state(const FrameArgs &a, int x, int y, float vx, float vy,
                                              float (&st)[NS])
@@ -310,7 +311,8 @@ __device__ __forceinline__ void update_pixel(const FrameArgs &a, int x, int y)
     const float v = a.unit_weight ? 1.0f : bload(array_rsrc(a.var, n * 4u), j * 4u, 0u);
 
     float st[NS];
-    if (!gather_state<NS>(a, x, y, vx, vy, st)) init_model<D>(a.p0, st + p_entry0(D), st + beta_entry0(D));
+    if (!gather_state<NS>(a, x, y, vx, vy, st))
+        init_model<D>(a.p0, st + p_entry0(D), st + beta_entry0(D));
 
     // Weight: inverse variance (or 1); 0 for any non-finite input.
     bool ok = finite(yc[0]) && finite(yc[1]) && finite(yc[2]);
@@ -573,9 +575,9 @@ hipError_t launch_step_d(bool f16, const FrameArgs &a, TileShape ts, hipStream_t
 // smaller, fixed grid the kernel is persistent and its workgroups loop (on
 // gfx9 a looping wave's first wait for its next loads also waits for its
 // previous stores, which made that form ~20% slower on the 16-stream mix).
-// The loop bookkeeping costs the batched kernel ~10 registers over the
-// per-frame kernel; the occupancy hint keeps d <= 8 at 5 waves per SIMD
-// (94 registers, no spills), as the per-frame kernel; d = 10 spills at 5.
+// The occupancy hint keeps d <= 8 at 5 waves per SIMD (96 registers, no
+// spills; the per-frame kernel, without a hint, takes 104 registers and 4
+// waves, and times the same with a hint of 5); d = 10 runs at 4.
 template <int D, typename InT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(D <= 8 ? 5 : 4)))
 batch_kernel(const BatchTable *__restrict__ tab)
@@ -673,7 +675,8 @@ constexpr int kBlendK = 2 * kBlendR + 1;  // window side
 // The occupancy hint caps registers: left alone, the scheduler keeps most of
 // a channel's LDS reads in flight and needs 168+ VGPRs at d = 8.
 template <int D, typename InT, bool PAPER>
-__global__ void __launch_bounds__(kBlendThreads) __attribute__((amdgpu_waves_per_eu(D <= 1 ? 5 : (D <= 7 ? 4 : (D <= 9 ? 3 : 2)))))
+__global__ void __launch_bounds__(kBlendThreads)
+__attribute__((amdgpu_waves_per_eu(D <= 1 ? 5 : (D <= 7 ? 4 : (D <= 9 ? 3 : 2)))))
 blend_kernel(const BlendArgs a)
 {
     constexpr int RPT = kBlendRPT;
