@@ -202,8 +202,10 @@ def test_c2_full_size_1080p_all_60_frames():
     _run(synth.c2())
 
 
-def test_c3_full_size_4k_first_frames():
-    _run(synth.c3(frames=5))
+def test_c3_full_size_4k_all_30_frames():
+    """The full 4K d = 10 FP16 recipe, every pixel of all 30 frames, through
+    the colour-LUT edit (frame 15) and the light change (frame 22)."""
+    _run(synth.c3())
 
 
 def _max_square_side(d):
