@@ -151,8 +151,9 @@ wrls_status wrls_set_hip_stream(wrls_stream *s, void *hip_stream);
  * high; tile_w_log2 in [0, log2(block_threads)].  Tiles are processed in
  * vertical strips of strip_tiles tiles (0 = the full image width), row by row
  * inside a strip.  Results do not depend on the shape: each pixel's
- * arithmetic is the same.  Default: 128 x 1 (128 threads), strip_tiles 0;
- * in paper mode (WRLS_W_PAPER) 64 x 2. */
+ * arithmetic is the same.  Default: strip_tiles 0 and 256 x 1 (256
+ * threads) when 256 divides the image width, else 128 x 1 (128 threads); in
+ * paper mode (WRLS_W_PAPER) 64 x 2 (128 threads). */
 wrls_status wrls_set_tile(wrls_stream *s, int32_t tile_w_log2, int32_t block_threads,
                           int32_t strip_tiles);
 

@@ -252,3 +252,30 @@ def test_maximum_size_d10_sampled_windows():
             assert e <= G1_TOL, (t, x0, y0, e)
     g.close()
     torch.cuda.synchronize()
+
+
+def test_every_launch_shape_bitwise_and_default_shapes():
+    """Results do not depend on the launch shape: every accepted tile shape
+    and strip width gives the default shape's outputs and state bitwise.  The
+    default is 256 x 1 when 256 divides the width, else 128 x 1."""
+    import torch
+    from paper_2106_08034_amd import wrls
+    assert wrls.Stream(512, 8, 8).tile == (8, 256, 0)
+    assert wrls.Stream(1920, 8, 8).tile == (7, 128, 0)
+    wl = synth.c2(width=197, height=45, frames=4)
+    frames = [tuple(to_dev(x) for x in (f.color, f.feats, f.var, f.motion)) for f in synth.frames(wl)]
+    ref = wrls.Stream(wl.width, wl.height, wl.d)
+    outs = [ref.step(*f).clone() for f in frames]
+    P0, B0 = ref.get_state()
+    shapes = [(0, 64, 0), (1, 64, 3), (6, 64, 0), (8, 256, 0), (8, 256, 1), (4, 256, 2), (0, 256, 0),
+              (7, 128, 2), (2, 128, 5)]
+    for tw, bt, sw in shapes:
+        log("case step shape %dx%d strip %d" % (1 << tw, bt >> tw, sw))
+        s = wrls.Stream(wl.width, wl.height, wl.d)
+        s.set_tile(tw, bt, sw)
+        for t, f in enumerate(frames):
+            assert torch.equal(s.step(*f), outs[t]), ((tw, bt, sw), t)
+        P, B = s.get_state()
+        assert torch.equal(P, P0) and torch.equal(B, B0), (tw, bt, sw)
+        s.close()
+    torch.cuda.synchronize()
