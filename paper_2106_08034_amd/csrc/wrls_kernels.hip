@@ -155,21 +155,38 @@ __device__ __forceinline__ bool gather_state(const FrameArgs &a, int x, int y, f
     const uint32_t W = (uint32_t)a.W;
     const uint32_t i00 = (uint32_t)y0 * W + (uint32_t)x0, i10 = (uint32_t)y0 * W + (uint32_t)x1;
     const uint32_t i01 = (uint32_t)y1 * W + (uint32_t)x0, i11 = (uint32_t)y1 * W + (uint32_t)x1;
-    // Bilinear in nested-lerp form (exact for a constant field).  One vector
-    // group per batch: its four taps (16 entries) are issued back to back,
-    // behind a scheduling barrier, before any is consumed.
+    // Bilinear in nested-lerp form (exact for a constant field).  The taps
+    // are issued GB vector groups at a time (4 GB 16-byte loads back to
+    // back, behind a scheduling barrier, before any is consumed): one group
+    // per batch up to 64 entries, two above (4K d = 10: 1109 -> 1092 us, at
+    // one wave per SIMD less; d = 8 and paper mode gain nothing from two,
+    // three are slower everywhere).
     const uint32_t v00 = vslot(i00, NS), v10 = vslot(i10, NS), v01 = vslot(i01, NS), v11 = vslot(i11, NS);
+    constexpr int GB = NS > 64 ? 2 : 1;
 #pragma unroll
-    for (int g = 0; g < G; g++) {
-        const uint32_t go = vgroup(g);
-        const f4_t t00 = *vec_at(a.state_in, go, v00), t10 = *vec_at(a.state_in, go, v10);
-        const f4_t t01 = *vec_at(a.state_in, go, v01), t11 = *vec_at(a.state_in, go, v11);
+    for (int g0 = 0; g0 < G; g0 += GB) {
+        f4_t t[GB][4];
+#pragma unroll
+        for (int q = 0; q < GB; q++) {
+            if (g0 + q < G) {
+                const uint32_t go = vgroup(g0 + q);
+                t[q][0] = *vec_at(a.state_in, go, v00);
+                t[q][1] = *vec_at(a.state_in, go, v10);
+                t[q][2] = *vec_at(a.state_in, go, v01);
+                t[q][3] = *vec_at(a.state_in, go, v11);
+            }
+        }
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int e = 0; e < 4; e++) {
-            const float top = fmaf(fx, t10[e] - t00[e], t00[e]);
-            const float bot = fmaf(fx, t11[e] - t01[e], t01[e]);
-            st[4 * g + e] = fmaf(fy, bot - top, top);
+        for (int q = 0; q < GB; q++) {
+            if (g0 + q < G) {
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    const float top = fmaf(fx, t[q][1][e] - t[q][0][e], t[q][0][e]);
+                    const float bot = fmaf(fx, t[q][3][e] - t[q][2][e], t[q][2][e]);
+                    st[4 * (g0 + q) + e] = fmaf(fy, bot - top, top);
+                }
+            }
         }
     }
     if constexpr (NS % 4 != 0) {
@@ -577,9 +594,12 @@ hipError_t launch_step_d(bool f16, const FrameArgs &a, TileShape ts, hipStream_t
 // previous stores, which made that form ~20% slower on the 16-stream mix).
 // The occupancy hint keeps d <= 8 at 5 waves per SIMD (96 registers, no
 // spills; the per-frame kernel, without a hint, takes 104 registers and 4
-// waves, and times the same with a hint of 5); d = 10 runs at 4.
+// waves, and times the same with a hint of 5) except d = 7, which would
+// spill at 5; d >= 9 runs at 3, as the per-frame kernel with its two-group
+// gather batches.
 template <int D, typename InT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(D <= 8 ? 5 : 4)))
+__global__ void __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(D == 7 ? 4 : (D <= 8 ? 5 : 3))))
 batch_kernel(const BatchTable *__restrict__ tab)
 {
     const int G = (int)gridDim.x;
