@@ -285,6 +285,16 @@ wrls_status wrls_batch_use_graph(wrls_batch *b, int32_t enable);
 wrls_status wrls_batch_step(wrls_batch *b, int32_t n, wrls_stream *const *streams,
                             const wrls_frame *frames);
 
+/* Device-to-device copy of `bytes` bytes, in the state kernels' access
+ * form: 16-byte loads and non-temporal 16-byte stores, one vector per
+ * thread.  A utility (for example to snapshot outputs), and the read+write
+ * bandwidth reference the benchmark reports beside the HBM peak.  dst and
+ * src are device pointers, 16-byte aligned, not overlapping; bytes is a
+ * multiple of 16 (0 is a no-op).  Stream-ordered on hip_stream (NULL: the
+ * null stream); returns without synchronising.  WRLS_EINVAL on a bad
+ * argument. */
+wrls_status wrls_device_copy(void *dst, const void *src, size_t bytes, void *hip_stream);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char *wrls_last_error(void);
 

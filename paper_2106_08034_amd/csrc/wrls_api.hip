@@ -729,6 +729,19 @@ wrls_status wrls_set_history(wrls_stream *s, const float *z)
     return WRLS_OK;
 }
 
+wrls_status wrls_device_copy(void *dst, const void *src, size_t bytes, void *hip_stream)
+{
+    if (bytes == 0) return WRLS_OK;
+    if (!dst || !src) return fail(WRLS_EINVAL, "dst and src are required");
+    if (!aligned(dst, 16) || !aligned(src, 16) || bytes % 16 != 0)
+        return fail(WRLS_EINVAL, "dst and src need 16-byte alignment and bytes a multiple of 16");
+    const uintptr_t d0 = (uintptr_t)dst, s0 = (uintptr_t)src;
+    if (d0 < s0 + bytes && s0 < d0 + bytes) return fail(WRLS_EINVAL, "dst and src overlap");
+    hipError_t e = wrls::launch_copy(dst, src, bytes / 16, static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return hip_fail(e, "copy launch");
+    return WRLS_OK;
+}
+
 const char *wrls_last_error(void) { return g_err; }
 
 const char *wrls_version(void) { return "libwrls 0.1 gfx950"; }

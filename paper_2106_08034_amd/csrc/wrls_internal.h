@@ -153,6 +153,8 @@ hipError_t launch_reset(float *state, int64_t npix, int d, int S, float p0, hipS
 hipError_t launch_convert(float *state, float *planes, int64_t npix, int d, int S, int k0,
                           int count, bool to_state, hipStream_t st);
 hipError_t launch_step(int d, bool f16, const FrameArgs &a, TileShape ts, hipStream_t st);
+// n16 16-byte vectors from src to dst (16-byte loads, non-temporal stores).
+hipError_t launch_copy(void *dst, const void *src, size_t n16, hipStream_t st);
 // The paper's own predictor and weight (d = 4, state with history).
 hipError_t launch_step_paper(bool f16, const FrameArgs &a, TileShape ts, hipStream_t st);
 // The 5x5 spatial blend of neighbour-model predictions; paper: p = [1, z]

@@ -541,6 +541,14 @@ __global__ void __launch_bounds__(256) reset_kernel(float *state, int64_t npix, 
     }
 }
 
+// Plain copy of n16 16-byte vectors, one per thread: the 16-byte loads and
+// non-temporal 16-byte stores of the state accesses, without the gather.
+__global__ void __launch_bounds__(256) copy_kernel(const f4_t *src, f4_t *dst, size_t n16)
+{
+    const size_t i = (size_t)blockIdx.x * 256u + threadIdx.x;
+    if (i < n16) __builtin_nontemporal_store(((gcf4_t *)src)[i], (gf4_t *)dst + i);
+}
+
 // Entries k0 .. k0 + count - 1 of every pixel between a state copy and
 // caller planes [count][npix].
 __global__ void __launch_bounds__(256) convert_kernel(float *state, float *planes, int64_t npix,
@@ -996,6 +1004,17 @@ hipError_t launch_reset(float *state, int64_t npix, int d, int S, float p0, hipS
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(reset_kernel, dim3((unsigned)blocks), dim3(256), 0, st, state, npix, d, S,
                        p0);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(void *dst, const void *src, size_t n16, hipStream_t st)
+{
+    if (n16 == 0) return hipSuccess;
+    const size_t blocks = (n16 + 255) / 256;
+    if (blocks > 0x7FFFFFFFu) return hipErrorInvalidValue;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(copy_kernel, dim3((unsigned)blocks), dim3(256), 0, st,
+                       static_cast<const f4_t *>(src), static_cast<f4_t *>(dst), n16);
     return hipGetLastError();
 }
 

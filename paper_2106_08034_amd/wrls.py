@@ -79,6 +79,7 @@ SIGNATURES = {
     "wrls_batch_use_graph": (ctypes.c_int, [_VP, ctypes.c_int32]),
     "wrls_batch_step": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.POINTER(_VP),
                                        ctypes.POINTER(wrls_frame)]),
+    "wrls_device_copy": (ctypes.c_int, [_VP, _VP, ctypes.c_size_t, _VP]),
     "wrls_last_error": (ctypes.c_char_p, []),
     "wrls_version": (ctypes.c_char_p, []),
 }
@@ -241,6 +242,15 @@ def wrls_get_history(h: int, z):
 
 def wrls_set_history(h: int, z):
     _check(lib().wrls_set_history(h, _ptr(z)))
+
+
+def wrls_device_copy(dst, src, nbytes: Optional[int] = None, hip_stream: Optional[int] = None):
+    """Copies nbytes (default: all of src) from tensor src to tensor dst on
+    the library's 16-byte copy kernel, on torch's current stream unless
+    hip_stream is given."""
+    n = src.numel() * src.element_size() if nbytes is None else nbytes
+    hs = _current_hip_stream() if hip_stream is None else hip_stream
+    _check(lib().wrls_device_copy(_ptr(dst), _ptr(src), n, hs))
 
 
 def wrls_last_error() -> str:

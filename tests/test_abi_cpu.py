@@ -177,3 +177,19 @@ def test_batch_and_stream_in_reject_bad_arguments_without_gpu():
     assert L.wrls_create_stream_in(ctypes.byref(p), ctypes.c_void_p(0x1000), need - 1, None,
                                    ctypes.byref(h)) == wrls.WRLS_EINVAL
     assert "needs" in wrls.wrls_last_error()
+
+
+def test_device_copy_rejects_bad_arguments_on_the_host():
+    """wrls_device_copy validates before any HIP call: null pointers,
+    misalignment, a size that is not a multiple of 16 and overlap are
+    rejected; zero bytes is a no-op.  (Fake addresses: nothing is launched.)"""
+    L = wrls.lib()
+    assert L.wrls_device_copy(None, None, 0, None) == wrls.WRLS_OK
+    assert L.wrls_device_copy(None, 4096, 16, None) == wrls.WRLS_EINVAL
+    assert L.wrls_device_copy(4096, None, 16, None) == wrls.WRLS_EINVAL
+    assert L.wrls_device_copy(4096 + 4, 8192, 16, None) == wrls.WRLS_EINVAL   # dst misaligned
+    assert L.wrls_device_copy(4096, 8192 + 8, 16, None) == wrls.WRLS_EINVAL   # src misaligned
+    assert L.wrls_device_copy(4096, 8192, 24, None) == wrls.WRLS_EINVAL       # not whole vectors
+    assert L.wrls_device_copy(4096, 4096 + 32, 64, None) == wrls.WRLS_EINVAL  # overlap
+    assert L.wrls_device_copy(4096 + 32, 4096, 64, None) == wrls.WRLS_EINVAL
+    assert "overlap" in wrls.wrls_last_error()

@@ -279,3 +279,20 @@ def test_every_launch_shape_bitwise_and_default_shapes():
         assert torch.equal(P, P0) and torch.equal(B, B0), (tw, bt, sw)
         s.close()
     torch.cuda.synchronize()
+
+
+def test_device_copy_bitwise():
+    """The library's copy kernel (the benchmark's bandwidth reference) copies
+    every byte, including a tail that is not a whole workgroup, and leaves
+    the bytes past the end untouched."""
+    import torch
+    from paper_2106_08034_amd import wrls
+    g = torch.Generator(device="cuda").manual_seed(5)
+    for n in (4, 1000, 1 << 20, (1 << 22) + 68):
+        src = torch.randn(n, device="cuda", generator=g)
+        dst = torch.full((n + 64,), 7.0, device="cuda")
+        wrls.wrls_device_copy(dst, src)
+        assert torch.equal(dst[:n], src) and torch.all(dst[n:] == 7.0), n
+    with pytest.raises(wrls.WrlsError):
+        wrls.wrls_device_copy(dst, src[1:5])  # misaligned source
+    torch.cuda.synchronize()
