@@ -207,3 +207,39 @@ def test_distinct_handles_from_two_host_threads():
     for i in range(2):
         for a, b in zip(seq_out[i], par_out[i]):
             assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("d", [1, 2, 4, 7, 9, 10])
+@pytest.mark.parametrize("in_dtype", ["f32", "f16"])
+def test_batch_every_d_bitwise(d, in_dtype):
+    """The batched kernel is compiled per d with its own occupancy hint, and
+    d >= 9 gathers two vector groups per batch: at each of these d, three
+    streams of different sizes stepped in one batched launch give bitwise
+    the outputs and state of the per-frame kernel."""
+    import torch
+    from paper_2106_08034_amd import wrls
+    rng = np.random.default_rng(40 + d)
+    sizes = [(70, 9), (131, 5), (64, 12)]
+    tdt = torch.float16 if in_dtype == "f16" else torch.float32
+    alone = [wrls.Stream(w, h, d, in_dtype=in_dtype) for (w, h) in sizes]
+    cs = torch.cuda.current_stream().cuda_stream
+    mixed = [wrls.Stream(w, h, d, in_dtype=in_dtype, hip_stream=cs) for (w, h) in sizes]
+    b = wrls.Batch(len(sizes), d, in_dtype, hip_stream=cs)
+    log("case batch d=%d %s" % (d, in_dtype))
+    for t in range(4):
+        frames = []
+        for (w, h) in sizes:
+            color = torch.from_numpy(rng.uniform(0, 1.5, (3, h, w)).astype(np.float32)).cuda().to(tdt)
+            feats = torch.from_numpy(rng.uniform(0, 1, (d - 1, h, w)).astype(np.float32)).cuda().to(tdt)
+            var = torch.from_numpy(np.exp(-3 + rng.standard_normal((h, w))).astype(np.float32)).cuda()
+            mot = torch.from_numpy(rng.uniform(-1.6, 1.6, (2, h, w)).astype(np.float32)).cuda()
+            frames.append((color, feats if d > 1 else None, var, mot))
+        outs = b.step(mixed, frames)
+        for k, (s, f) in enumerate(zip(alone, frames)):
+            assert torch.equal(s.step(*f), outs[k]), (d, in_dtype, t, k)
+    for s, m in zip(alone, mixed):
+        P0, B0 = s.get_state()
+        P1, B1 = m.get_state()
+        assert torch.equal(P0, P1) and torch.equal(B0, B1)
+    b.close()
+    torch.cuda.synchronize()
