@@ -455,6 +455,8 @@ struct wrls_batch {
     const wrls::BatchTable *knode_arg[2];  // storage the kernel node's argument points to
 };
 
+// C++ linkage: the helpers return HIP (C++) types
+extern "C++" {
 namespace {
 
 void drop_graphs(wrls_batch *b)
@@ -538,6 +540,7 @@ hipError_t enqueue_step(wrls_batch *b, int i, int32_t grid)
 }
 
 }  // namespace
+}  // extern "C++"
 
 wrls_status wrls_batch_create(int32_t max_streams, int32_t d, int32_t in_dtype, void *hip_stream,
                               wrls_batch **out)
