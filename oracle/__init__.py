@@ -61,7 +61,6 @@ def _load():
     lib.oracle_reset.argtypes = [ctypes.c_void_p]
     lib.oracle_frames.restype = ctypes.c_long
     lib.oracle_frames.argtypes = [ctypes.c_void_p]
-    lib.oracle_set_origin.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]
     lib.oracle_set_paper_params.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
                                             ctypes.c_double]
     lib.oracle_get_history.argtypes = [ctypes.c_void_p, dp]
@@ -117,8 +116,7 @@ class Oracle:
     """
 
     def __init__(self, width, height, d, lam=0.98, delta=1.0, var_floor=1e-6,
-                 wmode=W_INVVAR, interp=INTERP_BILINEAR, origin=(0, 0), alpha=0.75, h_bw=0.75,
-                 eps=1e-4):
+                 wmode=W_INVVAR, interp=INTERP_BILINEAR, alpha=0.75, h_bw=0.75, eps=1e-4):
         self._lib = _load()
         self.W, self.H, self.d = int(width), int(height), int(d)
         self.lam, self.delta = float(lam), float(delta)
@@ -127,9 +125,6 @@ class Oracle:
         if not h:
             raise ValueError("oracle_create rejected the parameters")
         self._h = h
-        # a crop of a larger image: source positions are rounded in that
-        # image's coordinates (see oracle_set_origin)
-        self._lib.oracle_set_origin(h, int(origin[0]), int(origin[1]))
         # paper mode (Eq. 12-13): history weight alpha, bandwidth h, epsilon
         self._lib.oracle_set_paper_params(h, float(alpha), float(h_bw), float(eps))
 

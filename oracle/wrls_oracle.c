@@ -11,10 +11,10 @@
  * baseline leg of the benchmark may load it.
  *
  * Arithmetic: IEEE binary64, round to nearest, built without fast-math and
- * with -ffp-contract=off.  The one place where floating point decides an
- * integer -- the source position j + v of the reprojection and its floor --
- * is evaluated in binary32, the precision of the GPU kernel, so both sides
- * pick the same taps and the same fractional weights.
+ * with -ffp-contract=off.  The reprojection source j + v (an integer pixel
+ * coordinate plus a binary32 motion value) is evaluated without rounding:
+ * the in-image test compares v with integer bounds, the tap is
+ * j + floor(v) and the bilinear fraction v - floor(v).
  *
  * Per pixel j and frame t (frames counted from 0):
  *   predictor   p = [1, f_1 .. f_{d-1}]                 (Sec. 5.1, Eq. 5)
@@ -73,7 +73,6 @@ typedef struct oracle {
     double var_floor;  /* smallest variance turned into a weight */
     int wmode;
     int interp;
-    int ox, oy;        /* position of pixel (0, 0) in a larger image (crops) */
     double alpha, h, eps;  /* paper mode: Eq. 12 history weight, Eq. 13 bandwidth and epsilon */
     long frames;       /* frames processed since creation or reset */
     /* Per-pixel state, pixel-major: P is d*d (full, row-major), beta 3*d. */
@@ -145,13 +144,6 @@ void oracle_reset(oracle *o)
 
 long oracle_frames(const oracle *o) { return o->frames; }
 
-/* Declares this image a crop of a larger one whose pixel (ox, oy) is this
- * image's pixel (0, 0).  The source position j + v is then rounded to
- * binary32 in the larger image's coordinates, exactly as for the full image,
- * so a crop reproduces the full image's arithmetic bit for bit (pixels whose
- * sources fall outside the crop restart, as at an image border). */
-void oracle_set_origin(oracle *o, int ox, int oy) { o->ox = ox; o->oy = oy; }
-
 /* Paper-mode parameters: alpha of Eq. 12, h and eps of Eq. 13. */
 void oracle_set_paper_params(oracle *o, double alpha, double h, double eps)
 {
@@ -165,40 +157,55 @@ int oracle_threads(void) { return omp_get_max_threads(); }
 void oracle_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
 
 /*
- * Reprojection (Sec. 5.3; Table 2 defines pi(v_j) = j + v_j as the pixel
- * position in the preceding frame).  Returns 1 and fills P, beta from the
- * previous frame's state, or returns 0 when pixel (x, y) has no valid source.
- * The source coordinate and its floor are taken in binary32.
+ * Source of pixel coordinate j along one axis of an image n pixels long
+ * (Sec. 5.3; Table 2 defines pi(v_j) = j + v_j as the pixel position in the
+ * preceding frame).  Returns 0 when j + v is not in [0, n - 1] (this also
+ * rejects a non-finite v).  Otherwise *i0 = floor(j + v) and *f = the
+ * fraction (j + v) - floor(j + v).  Since j is an integer these are
+ * j + floor(v) and v - floor(v), so nothing is rounded: the bounds j and
+ * n - 1 - j are exact, floor(v) of a binary32 value is exact in binary64,
+ * and so is v - floor(v) (to within 2^-54 for -1 < v < 0).  Nearest
+ * (round half up) picks floor(j + v + 1/2) = j + floor(v + 1/2).
  */
-static int reproject(const oracle *o, int x, int y, double vx_in, double vy_in,
+static int source_axis(int j, double v, int n, int nearest, int *i0, double *f)
+{
+    if (!(v >= -(double)j && v <= (double)(n - 1 - j))) return 0;
+    if (nearest) {
+        *i0 = j + (int)floor(v + 0.5);
+        *f = 0.0;
+    } else {
+        double fl = floor(v);
+        *i0 = j + (int)fl;
+        *f = v - fl;
+    }
+    return 1;
+}
+
+/*
+ * Reprojection (Sec. 5.3): fills P, beta of pixel (x, y) from the previous
+ * frame's state at (x + vx, y + vy) and returns 1, or returns 0 when the
+ * pixel has no valid source (non-finite motion, source outside the image).
+ */
+static int reproject(const oracle *o, int x, int y, double vx, double vy,
                      double *P, double *beta)
 {
     int d = o->d, W = o->W, H = o->H;
-    if (!isfinite(vx_in) || !isfinite(vy_in)) return 0;
-    /* binary32 position in the coordinates of the (possibly larger) image;
-     * removing the integer origin again is exact */
-    float sx = ((float)(x + o->ox) + (float)vx_in) - (float)o->ox;
-    float sy = ((float)(y + o->oy) + (float)vy_in) - (float)o->oy;
-    if (!(sx >= 0.0f && sx <= (float)(W - 1) && sy >= 0.0f && sy <= (float)(H - 1)))
+    int nearest = o->interp == ORACLE_INTERP_NEAREST;
+    int x0, y0;
+    double fx, fy;
+    if (!source_axis(x, vx, W, nearest, &x0, &fx) || !source_axis(y, vy, H, nearest, &y0, &fy))
         return 0;
 
-    if (o->interp == ORACLE_INTERP_NEAREST) {
-        int xn = (int)floorf(sx + 0.5f);
-        int yn = (int)floorf(sy + 0.5f);
-        if (xn > W - 1) xn = W - 1;
-        if (yn > H - 1) yn = H - 1;
-        size_t src = (size_t)yn * W + xn;
+    if (nearest) {
+        size_t src = (size_t)y0 * W + x0;
         memcpy(P, o->P_prev + src * d * d, sizeof(double) * d * d);
         memcpy(beta, o->beta_prev + src * 3 * d, sizeof(double) * 3 * d);
         return 1;
     }
 
-    /* Bilinear: the four pixels around (sx, sy), each entry of P and beta
+    /* Bilinear: the four pixels around the source, each entry of P and beta
      * blended with the textbook weights.  At the last column/row the second
      * tap coincides with the first (its weight is then zero anyway). */
-    float fx0 = floorf(sx), fy0 = floorf(sy);
-    int x0 = (int)fx0, y0 = (int)fy0;
-    double fx = (double)(sx - fx0), fy = (double)(sy - fy0);
     int x1 = x0 + 1 < W ? x0 + 1 : W - 1;
     int y1 = y0 + 1 < H ? y0 + 1 : H - 1;
     double w00 = (1.0 - fx) * (1.0 - fy);
@@ -217,23 +224,21 @@ static int reproject(const oracle *o, int x, int y, double vx_in, double vy_in,
 }
 
 /* The history z of the previous frame at the same source position, with the
- * same taps and weights as reproject() uses for the model. */
-static void reproject_history(const oracle *o, int x, int y, double vx_in, double vy_in,
+ * same taps and weights as reproject() uses for the model (called only for
+ * pixels that have a source). */
+static void reproject_history(const oracle *o, int x, int y, double vx, double vy,
                               double *zq)
 {
     int W = o->W, H = o->H;
-    float sx = ((float)(x + o->ox) + (float)vx_in) - (float)o->ox;
-    float sy = ((float)(y + o->oy) + (float)vy_in) - (float)o->oy;
-    if (o->interp == ORACLE_INTERP_NEAREST) {
-        int xn = (int)floorf(sx + 0.5f), yn = (int)floorf(sy + 0.5f);
-        if (xn > W - 1) xn = W - 1;
-        if (yn > H - 1) yn = H - 1;
-        for (int c = 0; c < 3; c++) zq[c] = o->z_prev[((size_t)yn * W + xn) * 3 + c];
+    int nearest = o->interp == ORACLE_INTERP_NEAREST;
+    int x0, y0;
+    double fx, fy;
+    if (!source_axis(x, vx, W, nearest, &x0, &fx) || !source_axis(y, vy, H, nearest, &y0, &fy))
+        return;
+    if (nearest) {
+        for (int c = 0; c < 3; c++) zq[c] = o->z_prev[((size_t)y0 * W + x0) * 3 + c];
         return;
     }
-    float fx0 = floorf(sx), fy0 = floorf(sy);
-    int x0 = (int)fx0, y0 = (int)fy0;
-    double fx = (double)(sx - fx0), fy = (double)(sy - fy0);
     int x1 = x0 + 1 < W ? x0 + 1 : W - 1;
     int y1 = y0 + 1 < H ? y0 + 1 : H - 1;
     for (int c = 0; c < 3; c++)

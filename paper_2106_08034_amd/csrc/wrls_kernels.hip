@@ -118,6 +118,16 @@ __device__ __forceinline__ void load_motion(const FrameArgs &a, uint32_t j, uint
 // the NS state entries of pixel (x, y) gathered from the previous frame's
 // state at (x, y) + v, v = (vx, vy).  Returns false when the pixel has no
 // valid source (first frame, non-finite motion, source outside the image).
+// The source position is not rounded: with x an integer, floor(x + v) =
+// x + floor(v), the fraction is v - floor(v), and 0 <= x + v <= W - 1 is
+// -x <= v <= W - 1 - x, whose bounds are exact in binary32.  floor(v) and
+// v - floor(v) are exact for v >= 0 and v <= -1; for -1 < v < 0 the fraction
+// 1 + v is rounded to nearest (error <= 2^-25; 1 when |v| < 2^-25, which
+// puts all the weight on the tap at x, the exact source's nearest).  A
+// binary32 sum x + v would instead move the source by up to half an ulp of
+// x: 1.2e-4 px near x = 3800, 4.9e-4 px past 8192.  Nearest rounds half up:
+// floor(x + v + 1/2) = x + floor(v) + (fraction >= 1/2), exact since a
+// rounded fraction 1 + v falls below 1/2 only where it is exact.
 // The vector groups (four entries per 16-byte access) come first, then the
 // scalar remainder.
 template <int NS>
@@ -126,16 +136,18 @@ __device__ __forceinline__ bool gather_state(const FrameArgs &a, int x, int y, f
 {
     constexpr int G = vec_planes(NS);
     if (a.fresh) return false;
-    const float sx = (float)x + vx;
-    const float sy = (float)y + vy;
     // NaN fails every comparison and +-inf lands outside: both restart.
-    if (!(sx >= 0.0f && sx <= (float)(a.W - 1) && sy >= 0.0f && sy <= (float)(a.H - 1)))
+    if (!(vx >= (float)(-x) && vx <= (float)(a.W - 1 - x) && vy >= (float)(-y) &&
+          vy <= (float)(a.H - 1 - y)))
         return false;
+    const float flx = floorf(vx), fly = floorf(vy);
+    const float fx = vx - flx, fy = vy - fly;
+    const int x0 = x + (int)flx, y0 = y + (int)fly;
     const uint32_t pitch = (uint32_t)a.pitch;
     const Rsrc src = array_rsrc(a.state_in, (uint32_t)NS * pitch * 4u);
     if (a.nearest) {
-        const int xn = min((int)floorf(sx + 0.5f), a.W - 1);
-        const int yn = min((int)floorf(sy + 0.5f), a.H - 1);
+        const int xn = min(x0 + (fx >= 0.5f ? 1 : 0), a.W - 1);
+        const int yn = min(y0 + (fy >= 0.5f ? 1 : 0), a.H - 1);
         const uint32_t i = (uint32_t)yn * (uint32_t)a.W + (uint32_t)xn;
         const uint32_t vi = vslot(i, NS);
 #pragma unroll
@@ -148,9 +160,6 @@ __device__ __forceinline__ bool gather_state(const FrameArgs &a, int x, int y, f
         for (int k = 4 * G; k < NS; k++) st[k] = bload(src, sslot(i, NS), sgroup(NS, k - 4 * G));
         return true;
     }
-    const float fx0 = floorf(sx), fy0 = floorf(sy);
-    const float fx = sx - fx0, fy = sy - fy0;
-    const int x0 = (int)fx0, y0 = (int)fy0;
     const int x1 = min(x0 + 1, a.W - 1), y1 = min(y0 + 1, a.H - 1);
     const uint32_t W = (uint32_t)a.W;
     const uint32_t i00 = (uint32_t)y0 * W + (uint32_t)x0, i10 = (uint32_t)y0 * W + (uint32_t)x1;

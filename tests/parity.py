@@ -14,6 +14,12 @@ Tolerance (FP32 state against the FP64 oracle, inputs identical):
   G2 P:       per pixel ||P_gpu - P_ref||_F / ||P_ref||_F <= 1e-4;
   G3 beta:    in prediction space with the last frame's predictor,
               |p . (beta_gpu - beta_ref)_c| / max(s, tau) <= 1e-4.
+
+How far the term scale relaxes the gate is reported, not hidden: every
+Pair also records the |y|-relative error |y_gpu - y_ref| / max(|y_ref|, tau)
+(its maximum and its 99.99th percentile per frame) and max(s) / RMS(y_ref).
+The synthetic workloads assert s <= S_RMS_BOUND * RMS, which bounds the
+gate in absolute terms: |y_gpu - y_ref| <= 1e-4 * max(|y_ref|, 16 RMS).
 """
 from __future__ import annotations
 
@@ -24,6 +30,9 @@ import numpy as np
 G1_TOL = 1e-4
 G2_TOL = 1e-4
 G3_TOL = 1e-4
+# largest term scale, in units of the frame's RMS output, that the synthetic
+# workloads may reach (measured up to ~8.4 on the 4K recipe's small crop)
+S_RMS_BOUND = 16.0
 
 
 def log(msg: str):
@@ -46,6 +55,13 @@ def g1(gpu: np.ndarray, ref: np.ndarray, scale=None) -> float:
     den = np.abs(ref) if scale is None else np.maximum(np.abs(ref), scale)
     den = np.maximum(den, max(tau, 1e-30))
     return float(np.max(np.abs(gpu.astype(np.float64) - ref) / den))
+
+
+def y_relative(gpu: np.ndarray, ref: np.ndarray) -> np.ndarray:
+    """|gpu - ref| / max(|ref|, 1e-3 RMS(ref)), elementwise: the relative
+    error with |y| as the denominator (reported beside G1)."""
+    tau = 1e-3 * float(np.sqrt(np.mean(ref.astype(np.float64) ** 2)))
+    return np.abs(gpu.astype(np.float64) - ref) / np.maximum(np.abs(ref), max(tau, 1e-30))
 
 
 def blend_scale(beta_ref: np.ndarray, p: np.ndarray) -> np.ndarray:
@@ -135,6 +151,10 @@ class Pair:
         self.paper = weight_mode == "paper"
         self.alpha = alpha
         self._z_prev = self._motion = None
+        # reported alongside G1: the |y|-relative error and the term scale
+        self.y_rel_max = 0.0
+        self.y_rel_p9999 = 0.0
+        self.s_rms_max = 0.0
 
     def _p(self, feats, shape):
         if self.paper:
@@ -155,7 +175,23 @@ class Pair:
         ref = self.ref.step(color, feats if use_f else None, var, motion)
         scale = term_scale(self.ref.get_beta(), self._p(feats, ref.shape[1:]))
         out = out.cpu().numpy()
+        self.note(out, ref, scale)
         return out, ref, g1(out, ref, scale)
+
+    def note(self, out, ref, scale):
+        """Records the |y|-relative error and max(s) / RMS of one frame."""
+        if not ref.size:
+            return
+        yr = y_relative(out, ref)
+        self.y_rel_max = max(self.y_rel_max, float(yr.max()))
+        self.y_rel_p9999 = max(self.y_rel_p9999, float(np.percentile(yr, 99.99)))
+        rms = float(np.sqrt(np.mean(ref ** 2)))
+        if rms > 0:
+            self.s_rms_max = max(self.s_rms_max, float(scale.max()) / rms)
+
+    def relaxation(self) -> str:
+        return ("|y|-relative error max %.3g, 99.99th pct %.3g; max s/RMS %.2f"
+                % (self.y_rel_max, self.y_rel_p9999, self.s_rms_max))
 
     def history_error(self) -> float:
         """Paper mode: max |z_gpu - z_ref| / max(|z_ref|, s_z, tau) of the
@@ -169,9 +205,9 @@ class Pair:
         scale = np.zeros_like(zr)
         if self._z_prev is not None:
             H, W = zr.shape[1:]
-            mv = np.zeros((2, H, W), np.float32) if self._motion is None else self._motion
-            sx = np.arange(W, dtype=np.float32)[None, :] + mv[0]
-            sy = np.arange(H, dtype=np.float32)[:, None] + mv[1]
+            mv = np.zeros((2, H, W)) if self._motion is None else self._motion.astype(np.float64)
+            sx = np.arange(W, dtype=np.float64)[None, :] + mv[0]  # j + v, exact
+            sy = np.arange(H, dtype=np.float64)[:, None] + mv[1]
             inside = np.isfinite(sx) & np.isfinite(sy) & (sx >= 0) & (sx <= W - 1) & (sy >= 0) & (sy <= H - 1)
             x0 = np.where(inside, np.floor(np.where(inside, sx, 0)), 0).astype(np.int64)
             y0 = np.where(inside, np.floor(np.where(inside, sy, 0)), 0).astype(np.int64)

@@ -32,7 +32,17 @@ def _dev(f):
     return (to_dev(f.color), to_dev(f.feats), to_dev(f.var), to_dev(f.motion))
 
 
-def test_batch_equals_alone_bitwise_and_matches_oracle():
+def _tiles(wls, shape):
+    tw, bt = 1 << shape[0], shape[1]
+    th = bt // tw
+    return sum(((wl.width + tw - 1) // tw) * ((wl.height + th - 1) // th) for wl in wls)
+
+
+@pytest.mark.parametrize("blocks_per_cu", [0, 1, -1])
+def test_batch_equals_alone_bitwise_and_matches_oracle(blocks_per_cu):
+    """blocks_per_cu 0: one workgroup per tile; 1 and -1: a fixed persistent
+    grid (one workgroup per CU, or as many as are resident) whose workgroups
+    loop over the tiles, advancing through the frame table as they go."""
     import oracle
     import torch
     from paper_2106_08034_amd import wrls
@@ -46,9 +56,15 @@ def test_batch_equals_alone_bitwise_and_matches_oracle():
     mixed = [wrls.Stream(wl.width, wl.height, wl.d, in_dtype="f16", hip_stream=cs) for wl in wls]
     b_plain = wrls.Batch(len(wls), 8, "f16", hip_stream=cs, use_graph=False)
     plain = [wrls.Stream(wl.width, wl.height, wl.d, in_dtype="f16", hip_stream=cs) for wl in wls]
+    shape = (7, 128)
+    b_graph.set_tile(shape[0], shape[1], blocks_per_cu)
+    b_plain.set_tile(shape[0], shape[1], blocks_per_cu)
+    if blocks_per_cu == 1:
+        cus = torch.cuda.get_device_properties(0).multi_processor_count
+        assert _tiles(wls, shape) > 2 * cus  # every workgroup loops
     refs = [oracle.Oracle(wl.width, wl.height, wl.d) for wl in wls]
     for t in range(T):
-        log("case batch mix frame %d" % t)
+        log("case batch mix blocks_per_cu=%d frame %d" % (blocks_per_cu, t))
         outs_a = [s.step(*dev[i][t]).clone() for i, s in enumerate(alone)]
         outs_g = b_graph.step(mixed, [dev[i][t] for i in range(len(wls))])
         outs_p = b_plain.step(plain, [dev[i][t] for i in range(len(wls))])
@@ -122,13 +138,15 @@ def test_stream_in_caller_memory_equals_library_allocation():
     torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("shape", [None, (8, 256, 0)])
+@pytest.mark.parametrize("shape", [None, (8, 256, 0), (8, 256, 1), (7, 128, -1)])
 def test_full_size_c4_mix_batch_equals_alone(shape):
     """The 16-stream mix at its real resolutions (640x480 .. 2560x1440,
     FP16, d = 8) for a few frames: the batched graph replay gives every
-    stream the bits of its own launch, with the default tile and with the
-    256 x 1 tile the benchmark's autotuner picks; the smallest stream also
-    matches the oracle (G1)."""
+    stream the bits of its own launch, with the default tile, with the
+    256 x 1 tile the benchmark's autotuner picks, and with persistent grids
+    (third entry 1: one workgroup per CU; -1: as many as are resident),
+    whose workgroups each loop over dozens of tiles; the smallest stream
+    also matches the oracle (G1)."""
     import oracle
     import torch
     from paper_2106_08034_amd import wrls
@@ -144,7 +162,7 @@ def test_full_size_c4_mix_batch_equals_alone(shape):
     mixed = [wrls.Stream(wl.width, wl.height, 8, in_dtype="f16", hip_stream=b.hip_stream) for wl in wls]
     if shape is not None:
         for s in alone:
-            s.set_tile(shape[0], shape[1], shape[2])
+            s.set_tile(shape[0], shape[1], 0)
     srcs = [synth.FrameSource(wl) for wl in wls]
     for t in range(T):
         host = [s.next() for s in srcs]
@@ -155,6 +173,11 @@ def test_full_size_c4_mix_batch_equals_alone(shape):
         torch.cuda.synchronize()
         for i in range(len(wls)):
             assert torch.equal(outs_a[i], outs_b[i]), (t, wls[i].name)
+        if t == T - 1:
+            for sa, sb in zip(alone, mixed):
+                Pa, Ba = sa.get_state()
+                Pb, Bb = sb.get_state()
+                assert torch.equal(Pa, Pb) and torch.equal(Ba, Bb)
         h = host[small]
         ref = o.step(h.color, h.feats, h.var, h.motion)
         e = g1(outs_b[small].cpu().numpy(), ref, term_scale(o.get_beta(), predictor(h.feats)))

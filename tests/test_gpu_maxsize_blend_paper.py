@@ -3,8 +3,9 @@ accepts (state copy just below 4 GiB, so the highest 32-bit buffer offsets
 are used), against the FP64 oracle on sampled windows.
 
 The GPU runs the whole image.  Its state is exported and loaded into small
-oracles covering each window plus a margin (placed at the crop's origin, so
-that source positions round as in the full image); the oracle then takes
+oracles covering each window plus a margin (the source position j + v is
+exact on both sides, so a crop sees the same taps and weights as the full
+image); the oracle then takes
 the same next step and/or blend on identical state and inputs.  Only window
 pixels are compared: they lie at least 4 pixels inside their crop (beyond
 the reach of the reprojection, the 3x3 clamp and the 5x5 blend) unless the
@@ -79,7 +80,7 @@ def test_blend_at_maximum_size_d10_fp16():
     torch.cuda.synchronize()
     for (x0, y0), c in _windows(side):
         cx0, cy0, cx1, cy1 = c
-        o = oracle.Oracle(cx1 - cx0, cy1 - cy0, d, origin=(cx0, cy0))
+        o = oracle.Oracle(cx1 - cx0, cy1 - cy0, d)
         Bc = _crop(B, c)
         o.set_state(unpack_P(_crop(P, c), d), Bc, frames=2)
         fc = _crop(feats, c).astype(np.float64)
@@ -122,7 +123,7 @@ def test_paper_step_and_blend_at_maximum_size():
     torch.cuda.synchronize()
     for (x0, y0), c in _windows(side):
         cx0, cy0, cx1, cy1 = c
-        o = oracle.Oracle(cx1 - cx0, cy1 - cy0, 4, wmode=oracle.W_PAPER, origin=(cx0, cy0),
+        o = oracle.Oracle(cx1 - cx0, cy1 - cy0, 4, wmode=oracle.W_PAPER,
                           eps=float(np.float32(1e-4)))
         o.set_state(unpack_P(_crop(P, c), 4), _crop(B, c), frames=1)
         o.set_history(_crop(z, c))

@@ -1,21 +1,23 @@
 """The serving loop on the GPU: sessions admitted by HBM footprint, frames
 continuously batched with two steps in flight; a session's outputs are
-bitwise those of the same session run alone."""
+bitwise those of the same session run alone, and match the FP64 oracle."""
 import pytest
 import torch
 
 import synth
-from parity import log, to_dev
+from parity import G1_TOL, g1, log, predictor, term_scale, to_dev
 
 pytestmark = pytest.mark.gpu
 
 
-def _pools(shapes, count=3):
+def _pools(shapes, count=3, host=None):
     pools = {}
     for i, (w, h) in enumerate(shapes):
         src = synth.FrameSource(synth.c5_frame_pool(w, h, count), stream=i)
-        pools[(w, h)] = [tuple(to_dev(a) for a in (f.color, f.feats, f.var, f.motion))
-                         for f in (src.next() for _ in range(count))]
+        frames = [src.next() for _ in range(count)]
+        if host is not None:
+            host[(w, h)] = frames
+        pools[(w, h)] = [tuple(to_dev(a) for a in (f.color, f.feats, f.var, f.motion)) for f in frames]
     return pools
 
 
@@ -33,16 +35,30 @@ def test_served_session_equals_alone_bitwise():
     sessions = [synth.Session(sid=i, width=shapes[i % 3][0], height=shapes[i % 3][1],
                               fps=60.0 + 10 * i, arrival=0.05 * i, duration=0.6 + 0.1 * i)
                 for i in range(8)]
-    pools = _pools(shapes)
+    host = {}
+    pools = _pools(shapes, host=host)
     srv = Server(budget_bytes=256 << 20, max_batch=8)
     log("case serve 8 small sessions")
     res, rec = srv.run(sessions, pools, seconds=5.0, record=3)
     log("serve result %s" % res)
     assert res["sessions_served"] == 8 and res["frames"] > 100
     assert len(rec) >= 20
-    alone = _replay_alone(sessions[3], pools[(sessions[3].width, sessions[3].height)], len(rec))
+    key = (sessions[3].width, sessions[3].height)
+    alone = _replay_alone(sessions[3], pools[key], len(rec))
     for k, (a, b) in enumerate(zip(alone, rec)):
         assert torch.equal(a, b), k
+    # the served session against the FP64 oracle, frame by frame (the pool
+    # cycles, as it did for the server)
+    import oracle
+    o = oracle.Oracle(key[0], key[1], 8)
+    worst = 0.0
+    for k, out in enumerate(rec):
+        f = host[key][k % len(host[key])]
+        ref = o.step(f.color, f.feats, f.var, f.motion)
+        e = g1(out.numpy(), ref, term_scale(o.get_beta(), predictor(f.feats)))
+        worst = max(worst, e)
+        assert e <= G1_TOL, (k, e)
+    log("served session vs oracle over %d frames: worst G1 %.3g" % (len(rec), worst))
 
 
 def test_budget_admission_queues_sessions():

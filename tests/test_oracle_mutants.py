@@ -23,16 +23,18 @@ MUTANTS = {
     "eq11_forgetting": ("(P[i * d + k] - q[i] * pP[k]) / lambda", "(P[i * d + k] - q[i] * pP[k]) * lambda"),
     "weight_is_std": ("return 1.0 / v;", "return 1.0 / sqrt(v);"),
     "prior_inverted": ("(i == k) ? 1.0 / o->delta : 0.0", "(i == k) ? o->delta : 0.0"),
-    "reproject_sign": ("float sx = ((float)(x + o->ox) + (float)vx_in) - (float)o->ox;",
-                       "float sx = ((float)(x + o->ox) - (float)vx_in) - (float)o->ox;"),
-    "origin_ignored": ("float sy = ((float)(y + o->oy) + (float)vy_in) - (float)o->oy;",
-                       "float sy = (float)y + (float)vy_in;"),
+    "reproject_sign": ("source_axis(x, vx, W, nearest, &x0, &fx)", "source_axis(x, -vx, W, nearest, &x0, &fx)"),
+    "source_position_binary32": ("    if (!(v >= -(double)j && v <= (double)(n - 1 - j))) return 0;\n",
+                                 "    float s32 = (float)j + (float)v;\n"
+                                 "    if (!(s32 >= 0.0f && s32 <= (float)(n - 1))) return 0;\n"
+                                 "    v = (double)(s32 - (float)j);\n"),
+    "bilinear_fraction_sign": ("        *f = v - fl;", "        *f = fl - v + 1.0;"),
     "bilinear_weights_swapped": ("double w10 = fx * (1.0 - fy);\n    double w01 = (1.0 - fx) * fy;",
                                  "double w10 = (1.0 - fx) * fy;\n    double w01 = fx * (1.0 - fy);"),
     "bilinear_tap_transposed": ("size_t s00 = (size_t)y0 * W + x0, s10 = (size_t)y0 * W + x1;",
                                 "size_t s00 = (size_t)y0 * W + x0, s10 = (size_t)y1 * W + x0;"),
-    "border_check_loose": ("sx <= (float)(W - 1)", "sx < (float)W"),
-    "nearest_truncates": ("int xn = (int)floorf(sx + 0.5f);", "int xn = (int)floorf(sx);"),
+    "border_check_loose": ("v <= (double)(n - 1 - j)", "v < (double)(n - j)"),
+    "nearest_truncates": ("*i0 = j + (int)floor(v + 0.5);", "*i0 = j + (int)floor(v);"),
     "output_a_priori": ("        out[c] = acc;\n", "        out[c] = prior_out ? prior_out[c] : acc;\n"),
     "features_reversed": ("p[i] = feats[(size_t)(i - 1) * n + j];", "p[i] = feats[(size_t)(d - 1 - i) * n + j];"),
     "outlier_not_skipped": ("    if (!isfinite(var) || var < 0.0) return 0.0;\n", ""),

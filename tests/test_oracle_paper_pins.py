@@ -129,8 +129,7 @@ def test_history_reprojects_bilinearly():
     motion = np.stack([tx - X, ty - Y]).astype(np.float32).astype(np.float64)
     o.step(col, None, None, motion)
     zq = (o.get_history() - (1 - ALPHA) * col) / ALPHA
-    sx = (X.astype(np.float32) + motion[0].astype(np.float32)).astype(np.float64)
-    sy = (Y.astype(np.float32) + motion[1].astype(np.float32)).astype(np.float64)
+    sx, sy = X + motion[0], Y + motion[1]  # j + v, exact in binary64 here
     np.testing.assert_allclose(zq, a + b * sx + c * sy + e * sx * sy, rtol=1e-10, atol=1e-10)
 
 

@@ -263,8 +263,8 @@ def test_bilinear_reprojection_exact_on_bilinear_fields():
     motion[1, 2, 3] = np.nan                         # disoccluded
     motion[0, 3, 4] = W - 0.5 - 4                    # lands between the last column and W
     motion[1, 3, 4] = 0.0
-    sx = (xs.astype(np.float32) + motion[0].astype(np.float32)).astype(np.float64)
-    sy = (ys_.astype(np.float32) + motion[1].astype(np.float32)).astype(np.float64)
+    sx = xs + motion[0]  # exact in binary64 for these sizes
+    sy = ys_ + motion[1]
     p = rng.uniform(0, 1, size=(d - 1, H, W))
     out = o.step(np.zeros((3, H, W)), p, np.full((H, W), np.inf), motion)
     P, beta = o.get_state()
@@ -294,10 +294,10 @@ def test_nearest_reprojection_is_a_gather():
     P, beta = o.get_state()
     for y in range(H):
         for x in range(W):
-            sx = np.float32(x) + np.float32(motion[0, y, x])
-            sy = np.float32(y) + np.float32(motion[1, y, x])
+            sx = Fraction(x) + Fraction(float(motion[0, y, x]))
+            sy = Fraction(y) + Fraction(float(motion[1, y, x]))
             if 0 <= sx <= W - 1 and 0 <= sy <= H - 1:
-                xn, yn = int(np.floor(sx + np.float32(0.5))), int(np.floor(sy + np.float32(0.5)))
+                xn, yn = int(np.floor(sx + Fraction(1, 2))), int(np.floor(sy + Fraction(1, 2)))
                 assert np.array_equal(P[:, :, y, x], P0[:, :, yn, xn] / lam)
                 assert np.array_equal(beta[:, :, y, x], B0[:, :, yn, xn])
             else:
@@ -370,18 +370,18 @@ def test_region_of_interest_matches_full_frame():
 
 
 @pytest.mark.parametrize("axis", [0, 1])
-def test_crop_with_origin_reproduces_full_image_bitwise(axis):
-    """A crop declared at its origin rounds source positions like the full
-    image (binary32 rounding of x + v depends on |x|), so pixels whose
-    motion chains stay inside the crop match the full image bitwise.
-    axis 0: a horizontal pan across x ~ 2900; axis 1: a vertical pan across
-    y ~ 2900."""
+def test_crop_reproduces_full_image_bitwise(axis):
+    """The source position j + v is evaluated exactly, so it does not depend
+    on where the pixel sits: a crop of the image, given the crop's inputs,
+    reproduces the full image bitwise for pixels whose motion chains stay
+    inside it.  axis 0: a horizontal pan across x ~ 2900; axis 1: a vertical
+    pan across y ~ 2900 (where binary32 x + v would be off by up to 1.2e-4)."""
     rng = np.random.default_rng(12)
     T, d, long_, short = 4, 4, 3000, 6
     H, W = (short, long_) if axis == 0 else (long_, short)
     ps, ys, var = _inputs(rng, T, H, W, d)
     motion = np.zeros((T, 2, H, W))
-    motion[:, axis] = 2.3
+    motion[:, axis] = np.float32(2.3)
     full = oracle.Oracle(W, H, d)
     for t in range(T):
         out_full = full.step(ys[t], ps[t], var[t], motion[t])
@@ -389,18 +389,55 @@ def test_crop_with_origin_reproduces_full_image_bitwise(axis):
     sl = (slice(None), slice(None), slice(a0, a1)) if axis == 0 else (slice(None), slice(a0, a1), slice(None))
     sl2 = sl[1:]
     cw, ch = (a1 - a0, H) if axis == 0 else (W, a1 - a0)
-    crop = oracle.Oracle(cw, ch, d, origin=(a0, 0) if axis == 0 else (0, a0))
-    local = oracle.Oracle(cw, ch, d)
+    crop = oracle.Oracle(cw, ch, d)
     for t in range(T):
-        args = (ys[t][sl], ps[t][sl], var[t][sl2], motion[t][sl])
-        out_crop = crop.step(*args)
-        out_local = local.step(*args)
+        out_crop = crop.step(ys[t][sl], ps[t][sl], var[t][sl2], motion[t][sl])
     n_ok = (a1 - a0) - int(2.3 * T) - 2
     keep = (slice(None), slice(None), slice(0, n_ok)) if axis == 0 else (slice(None), slice(0, n_ok), slice(None))
-    ref = out_full[sl][keep]
-    assert np.array_equal(out_crop[keep], ref)
-    # without the origin, binary32 rounding of the source position differs
-    assert not np.array_equal(out_local[keep], ref)
+    assert np.array_equal(out_crop[keep], out_full[sl][keep])
+
+
+def test_bilinear_reprojection_exact_at_large_coordinates():
+    """pi(v_j) = j + v_j holds exactly at the widest accepted image (16384
+    pixels), where binary32 spacing is 2^-10 px: every state entry set to a
+    bilinear field a + b x + c y + e x y, one weight-0 step with sub-pixel
+    motion of either sign, and the reprojected state must equal the field at
+    the exact source position; P is aged by 1/lambda.  Sources just past the
+    last column by one binary32 ulp of the motion (which a binary32 sum
+    x + v would round onto the last column) restart, and a source exactly on
+    the last column does not."""
+    rng = np.random.default_rng(21)
+    H, W, d, lam, delta = 2, 16384, 2, 0.9, 2.0
+    Pf, Pc = _bilinear_field(rng, d * d, H, W)
+    Bf, Bc = _bilinear_field(rng, 3 * d, H, W)
+    o = oracle.Oracle(W, H, d, lam=lam, delta=delta)
+    o.set_state(Pf.reshape(d, d, H, W), Bf.reshape(3, d, H, W), frames=1)
+    vx = rng.choice(np.array([0.3, -0.7, 1.17, -2.61, 0.013], np.float32), size=(H, W)).astype(np.float64)
+    vx[:, :8] = np.abs(vx[:, :8])                       # keep the first columns inside
+    vx[:, -8:] = -np.abs(vx[:, -8:])                    # and the last ones
+    vy = np.zeros((H, W))
+    vy[0] = np.float32(0.25)
+    vy[1] = np.float32(-0.75)
+    x_edge = W - 3
+    up = float(np.nextafter(np.float32(2.0), np.float32(3.0)))  # 2 + 2^-22
+    vx[0, x_edge] = 2.0                                   # exactly on the last column
+    vx[1, x_edge] = up                                    # 2.4e-7 px past it
+    motion = np.stack([vx, vy])
+    xs = np.arange(W)[None, :] + np.zeros((H, 1))
+    ys_ = np.arange(H)[:, None] + np.zeros((1, W))
+    sx, sy = xs + motion[0], ys_ + motion[1]             # exact in binary64 here
+    assert float(np.float32(x_edge) + np.float32(up)) == W - 1  # binary32 would call it inside
+    p = rng.uniform(0, 1, size=(d - 1, H, W))
+    o.step(np.zeros((3, H, W)), p, np.full((H, W), np.inf), motion)
+    P, beta = o.get_state()
+    a, b, c, e = Pc
+    Pexp = ((a + b * sx + c * sy + e * sx * sy) / lam).reshape(d, d, H, W)
+    a, b, c, e = Bc
+    Bexp = (a + b * sx + c * sy + e * sx * sy).reshape(3, d, H, W)
+    Pexp[:, :, 1, x_edge] = np.eye(d) / delta / lam
+    Bexp[:, :, 1, x_edge] = 0.0
+    np.testing.assert_allclose(P, Pexp, rtol=1e-12, atol=1e-9)
+    np.testing.assert_allclose(beta, Bexp, rtol=1e-12, atol=1e-9)
 
 
 def test_results_do_not_depend_on_thread_count():
