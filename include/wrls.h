@@ -92,7 +92,21 @@ typedef struct {
     float alpha;            /* WRLS_W_PAPER: history weight of Eq. 12, in [0, 1] */
     float h;                /* WRLS_W_PAPER: bandwidth of Eq. 13, > 0, 1/h^2 finite */
     float eps;              /* WRLS_W_PAPER: epsilon of Eq. 13, > 0 (finite) */
-    int32_t reserved[2];    /* must be zero */
+    /* Automatic forgetting factor.  The paper fixes lambda and names its
+     * automatic selection as future work (Sec. 7.6).  With sigma0 > 0 the
+     * library chooses it per pixel and frame by the rule of Fortescue,
+     * Kershenbaum and Ydstie (Automatica 17, 1981): lambda keeps the
+     * weighted a-posteriori error information of the pixel's fit at sigma0.
+     * With the forgetting of Eq. 10-11 that is the positive root of
+     *   lambda^2 + (b / sigma0 + a - 1) lambda - a = 0,
+     *   a = w p P p^T,  b = w sum_c e_c^2  (e_c the residual of Eq. 8),
+     * which lies in (0, 1], limited to [lambda_min, lambda]: the lambda
+     * above becomes the upper limit.  With inverse-variance weights
+     * E[b] is about 3 (1 + a), so sigma0 = 3 N sets a memory of about N
+     * frames for a fitting model and forgets faster when the residuals grow
+     * (an appearance change, a disocclusion the motion missed). */
+    float sigma0;           /* 0: lambda fixed (default); > 0 or +inf: automatic */
+    float lambda_min;       /* automatic: lower limit, in (0, lambda]; ignored when sigma0 = 0 */
 } wrls_params;
 
 typedef struct wrls_stream wrls_stream;  /* opaque, owned by the library */
@@ -100,7 +114,8 @@ typedef struct wrls_stream wrls_stream;  /* opaque, owned by the library */
 /* Fills *p with defaults for a width x height image and predictor length d:
  * lambda 0.98, delta 1, var_floor 1e-6, FP32 inputs, inverse-variance
  * weights, bilinear reprojection; alpha 0.75, h 0.75, eps 1e-4 (the values
- * Sec. 5.3 and 6 use).  A null p is ignored. */
+ * Sec. 5.3 and 6 use); fixed lambda (sigma0 0, lambda_min 0).  A null p is
+ * ignored. */
 void wrls_params_default(wrls_params *p, int32_t width, int32_t height, int32_t d);
 
 /* Checks a parameter block without touching the GPU: WRLS_OK or

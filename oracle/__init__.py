@@ -69,8 +69,10 @@ def _load():
     lib.oracle_threads.argtypes = []
     lib.oracle_set_threads.argtypes = [ctypes.c_int]
     lib.oracle_step.restype = ctypes.c_int
-    lib.oracle_step.argtypes = [ctypes.c_void_p, dp, dp, dp, dp, dp, dp,
+    lib.oracle_step.argtypes = [ctypes.c_void_p, dp, dp, dp, dp, dp, dp, dp, dp,
                                 ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.oracle_set_forgetting.restype = ctypes.c_int
+    lib.oracle_set_forgetting.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double]
     lib.oracle_get_state.argtypes = [ctypes.c_void_p, dp, dp]
     lib.oracle_get_beta.argtypes = [ctypes.c_void_p, dp]
     lib.oracle_set_state.argtypes = [ctypes.c_void_p, dp, dp, ctypes.c_long]
@@ -110,13 +112,17 @@ class Oracle:
 
     lam: forgetting factor; delta: prior precision (P starts at I/delta,
     beta at 0); var_floor: smallest variance turned into a weight.
+    sigma0 > 0: automatic forgetting factor (Fortescue, Kershenbaum and
+    Ydstie): per pixel and step, lambda keeps the weighted a-posteriori
+    error information at sigma0, limited to [lam_min, lam].
     wmode W_PAPER (d = 4): the predictor is the temporal feature of Eq. 12
     (alpha) and the weight that of Eq. 13 (h_bw, eps); features and variance
     are then not used.
     """
 
     def __init__(self, width, height, d, lam=0.98, delta=1.0, var_floor=1e-6,
-                 wmode=W_INVVAR, interp=INTERP_BILINEAR, alpha=0.75, h_bw=0.75, eps=1e-4):
+                 wmode=W_INVVAR, interp=INTERP_BILINEAR, alpha=0.75, h_bw=0.75, eps=1e-4,
+                 sigma0=0.0, lam_min=None):
         self._lib = _load()
         self.W, self.H, self.d = int(width), int(height), int(d)
         self.lam, self.delta = float(lam), float(delta)
@@ -127,6 +133,9 @@ class Oracle:
         self._h = h
         # paper mode (Eq. 12-13): history weight alpha, bandwidth h, epsilon
         self._lib.oracle_set_paper_params(h, float(alpha), float(h_bw), float(eps))
+        lo = self.lam if lam_min is None else float(lam_min)
+        if self._lib.oracle_set_forgetting(h, float(sigma0), lo) != 0:
+            raise ValueError("oracle_set_forgetting rejected sigma0=%r, lam_min=%r" % (sigma0, lam_min))
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -141,12 +150,15 @@ class Oracle:
     def reset(self):
         self._lib.oracle_reset(self._h)
 
-    def step(self, color, feats, var, motion=None, roi=None, want_prior=False):
+    def step(self, color, feats, var, motion=None, roi=None, want_prior=False,
+             want_lambda=False, want_scale=False):
         """Denoise one frame.  color (3,H,W); feats (d-1,H,W) or None when
         d = 1; var (H,W) or None; motion (2,H,W) or None (= zero).
         roi = (x0, y0, x1, y1) restricts the computed pixels.  Returns the
-        a-posteriori prediction (3,H,W) float64, and the a-priori one too when
-        want_prior."""
+        a-posteriori prediction (3,H,W) float64; with any want_* flag, a
+        tuple of it and, in this order, the a-priori prediction (3,H,W), the
+        forgetting factor of each pixel (H,W), and the magnitude of the
+        output's terms sum_i |p_i beta_c,i| (3,H,W) that were asked for."""
         W, H, d = self.W, self.H, self.d
         c = _f64(color, (3, H, W))
         f = _f64(feats, (d - 1, H, W)) if (d > 1 and feats is not None) else None
@@ -154,12 +166,16 @@ class Oracle:
         m = _f64(motion, (2, H, W)) if motion is not None else None
         out = np.zeros((3, H, W), np.float64)
         prior = np.zeros((3, H, W), np.float64) if want_prior else None
+        lam = np.zeros((H, W), np.float64) if want_lambda else None
+        scale = np.zeros((3, H, W), np.float64) if want_scale else None
         x0, y0, x1, y1 = roi if roi is not None else (0, 0, W, H)
         rc = self._lib.oracle_step(self._h, _ptr(c), _ptr(f), _ptr(v), _ptr(m), _ptr(out),
-                                   _ptr(prior), int(x0), int(y0), int(x1), int(y1))
+                                   _ptr(prior), _ptr(lam), _ptr(scale),
+                                   int(x0), int(y0), int(x1), int(y1))
         if rc != 0:
             raise ValueError("oracle_step rejected the region %r" % (roi,))
-        return (out, prior) if want_prior else out
+        extra = [a for a, want in ((prior, want_prior), (lam, want_lambda), (scale, want_scale)) if want]
+        return tuple([out] + extra) if extra else out
 
     def blend(self, feats, sigma_s, sigma_r):
         """The 5x5 spatial blend of neighbour-model predictions (Sec. 5.3) on

@@ -30,6 +30,9 @@
  *   coeffs      beta(t) = beta(t-1) + q e               (Eq. 9)
  *   inv. cov.   P(t) = (P - q (p P)) / lambda           (Eq. 11)
  *   output      yhat = p beta^T(t)                      (Eq. 6, a posteriori)
+ * The forgetting factor is fixed, or chosen per pixel and step by the rule
+ * of Fortescue, Kershenbaum and Ydstie (below; the paper leaves automatic
+ * selection to future work, Sec. 7.6).
  * Colour channels share P and w and keep one beta row each (Sec. 5.1 treats
  * channels independently with the same predictor).
  *
@@ -68,7 +71,9 @@
 
 typedef struct oracle {
     int W, H, d;
-    double lambda;     /* forgetting factor (Sec. 5.2) */
+    double lambda;     /* forgetting factor (Sec. 5.2); the upper limit of an automatic one */
+    double sigma0;     /* automatic forgetting: prescribed information (0: lambda fixed) */
+    double lambda_min; /* automatic forgetting: lower limit */
     double delta;      /* prior precision: P0 = I / delta */
     double var_floor;  /* smallest variance turned into a weight */
     int wmode;
@@ -148,6 +153,17 @@ long oracle_frames(const oracle *o) { return o->frames; }
 void oracle_set_paper_params(oracle *o, double alpha, double h, double eps)
 {
     o->alpha = alpha; o->h = h; o->eps = eps;
+}
+
+/* Automatic forgetting factor (see forgetting_factor): sigma0 > 0 turns it
+ * on (0 turns it off), lambda_min in (0, lambda] limits it from below. */
+int oracle_set_forgetting(oracle *o, double sigma0, double lambda_min)
+{
+    if (!(sigma0 >= 0.0)) return -1;
+    if (sigma0 > 0.0 && !(lambda_min > 0.0 && lambda_min <= o->lambda)) return -1;
+    o->sigma0 = sigma0;
+    o->lambda_min = lambda_min;
+    return 0;
 }
 
 /* Threads the per-row loop of oracle_step runs on. */
@@ -305,18 +321,56 @@ static double sample_weight(const oracle *o, const double *y, const double *p, d
 }
 
 /*
+ * Automatic forgetting factor, after Fortescue, Kershenbaum and Ydstie,
+ * "Implementation of self-tuning regulators with variable forgetting
+ * factors", Automatica 17 (1981): lambda is chosen at every step so that the
+ * weighted a-posteriori error information of the fit stays at a prescribed
+ * value Sigma0.  With the forgetting applied as in Eq. 10-11 (the old
+ * information is discounted by lambda before the sample enters), that
+ * information obeys V(t) = lambda V(t-1) + w sum_c e_c eps_c, where e_c is
+ * the a-priori residual of channel c (Eq. 8) and eps_c = e_c lambda /
+ * (lambda + w s) the a-posteriori one, s = p P p^T with the previous P.
+ * Requiring V(t) = V(t-1) = Sigma0 gives
+ *     (1 - lambda) (lambda + a) Sigma0 = lambda b,   a = w s,  b = w sum_c e_c^2,
+ * i.e. lambda^2 + (b / Sigma0 + a - 1) lambda - a = 0, whose positive root
+ * lies in (0, 1] (it is 1 when b = 0).  The root is then limited to
+ * [lambda_min, lambda]: the stream's lambda is the upper limit.  A sample of
+ * weight 0 carries no information: the root is 1.  sigma0 = 0 keeps lambda.
+ * y: colour, pred: the a-priori predictions p beta_c^T(t-1).
+ */
+static double forgetting_factor(const oracle *o, double w, double s, const double *y,
+                                const double *pred)
+{
+    if (o->sigma0 == 0.0) return o->lambda;
+    double lam = 1.0;
+    if (w > 0.0) {
+        double e2 = 0.0;
+        for (int c = 0; c < 3; c++) e2 += (y[c] - pred[c]) * (y[c] - pred[c]);
+        double a = w * s, b = w * e2;
+        double B = b / o->sigma0 + a - 1.0;
+        lam = (-B + sqrt(B * B + 4.0 * a)) / 2.0;
+    }
+    if (lam > o->lambda) lam = o->lambda;
+    if (lam < o->lambda_min) lam = o->lambda_min;
+    return lam;
+}
+
+/*
  * One wRLS update of one pixel, in place on (P, beta).  y: noisy colour,
  * p: predictor, w: weight.  prior_out (may be NULL) receives p beta^T(t-1),
- * out receives p beta^T(t).
+ * out receives p beta^T(t), scale_out (may be NULL) the magnitude of the
+ * terms of that sum, sum_i |p_i beta_c,i(t)| (for error measures).  Returns
+ * the forgetting factor of this step.
  */
-static void update_pixel(const oracle *o, double *P, double *beta, const double *p,
-                         const double *y, double w, double *prior_out, double *out)
+static double update_pixel(const oracle *o, double *P, double *beta, const double *p,
+                           const double *y, double w, double *prior_out, double *out,
+                           double *scale_out)
 {
     int d = o->d;
-    double lambda = o->lambda;
     double Ppt[32];   /* P p^T, a column */
     double pP[32];    /* p P, a row */
     double q[32];
+    double pred_prior[3];
 
     for (int i = 0; i < d; i++) {
         double acc = 0.0;
@@ -330,6 +384,12 @@ static void update_pixel(const oracle *o, double *P, double *beta, const double 
     }
     double pPpt = 0.0;
     for (int i = 0; i < d; i++) pPpt += p[i] * Ppt[i];
+    for (int c = 0; c < 3; c++) {
+        double acc = 0.0;
+        for (int i = 0; i < d; i++) acc += p[i] * beta[c * d + i];
+        pred_prior[c] = acc;
+    }
+    double lambda = forgetting_factor(o, w, pPpt, y, pred_prior);
 
     /* Eq. 14.  At w = 0 the gain is its limit, zero. */
     if (w > 0.0) {
@@ -341,8 +401,7 @@ static void update_pixel(const oracle *o, double *P, double *beta, const double 
 
     for (int c = 0; c < 3; c++) {
         double *b = beta + c * d;
-        double pred = 0.0;
-        for (int i = 0; i < d; i++) pred += p[i] * b[i];
+        double pred = pred_prior[c];
         if (prior_out) prior_out[c] = pred;
         if (w > 0.0) {
             double e = y[c] - pred;                       /* Eq. 8 */
@@ -355,10 +414,15 @@ static void update_pixel(const oracle *o, double *P, double *beta, const double 
             P[i * d + k] = (P[i * d + k] - q[i] * pP[k]) / lambda;
 
     for (int c = 0; c < 3; c++) {                          /* Eq. 6 */
-        double acc = 0.0;
-        for (int i = 0; i < d; i++) acc += p[i] * beta[c * d + i];
+        double acc = 0.0, mag = 0.0;
+        for (int i = 0; i < d; i++) {
+            acc += p[i] * beta[c * d + i];
+            mag += fabs(p[i] * beta[c * d + i]);
+        }
         out[c] = acc;
+        if (scale_out) scale_out[c] = mag;
     }
+    return lambda;
 }
 
 /*
@@ -367,13 +431,15 @@ static void update_pixel(const oracle *o, double *P, double *beta, const double 
  *   var [H][W] (ignored in unit-weight mode, may then be NULL),
  *   motion [2][H][W] (vx then vy, pixels, backward; may be NULL = zero).
  * out [3][H][W] receives the a-posteriori prediction, prior [3][H][W] (may be
- * NULL) the a-priori one.  Only pixels in the half-open rectangle
+ * NULL) the a-priori one, lam [H][W] (may be NULL) each pixel's forgetting
+ * factor of this step, scale [3][H][W] (may be NULL) the magnitude of the
+ * terms of the output, sum_i |p_i beta_c,i|.  Only pixels in the half-open rectangle
  * [x0, x1) x [y0, y1) are computed; elsewhere the state of this frame and the
  * outputs are left unspecified.  Returns 0, or -1 on a bad rectangle.
  */
 int oracle_step(oracle *o, const double *color, const double *feats, const double *var,
-                const double *motion, double *out, double *prior,
-                int x0, int y0, int x1, int y1)
+                const double *motion, double *out, double *prior, double *lam,
+                double *scale, int x0, int y0, int x1, int y1)
 {
     int W = o->W, H = o->H, d = o->d;
     if (x0 < 0 || y0 < 0 || x1 > W || y1 > H || x0 > x1 || y0 > y1) return -1;
@@ -393,7 +459,7 @@ int oracle_step(oracle *o, const double *color, const double *feats, const doubl
             size_t j = (size_t)y * W + x;
             double *P = o->P_cur + j * d * d;
             double *beta = o->beta_cur + j * 3 * d;
-            double p[32], yc[3], o3[3], pr3[3];
+            double p[32], yc[3], o3[3], pr3[3], sc3[3];
 
             for (int c = 0; c < 3; c++) yc[c] = color[(size_t)c * n + j];
             int have = 0;
@@ -428,10 +494,12 @@ int oracle_step(oracle *o, const double *color, const double *feats, const doubl
                         if (!isfinite(p[i])) p[i] = 0.0;
             }
 
-            update_pixel(o, P, beta, p, yc, w, pr3, o3);
+            double lam_j = update_pixel(o, P, beta, p, yc, w, pr3, o3, sc3);
+            if (lam) lam[j] = lam_j;
             for (int c = 0; c < 3; c++) {
                 out[(size_t)c * n + j] = o3[c];
                 if (prior) prior[(size_t)c * n + j] = pr3[c];
+                if (scale) scale[(size_t)c * n + j] = sc3[c];
             }
         }
     }

@@ -129,8 +129,11 @@ wrls_status wrls_params_validate(const wrls_params *p)
     }
     if (p->interp != WRLS_INTERP_BILINEAR && p->interp != WRLS_INTERP_NEAREST)
         return fail(WRLS_EINVAL, "interp = %d unknown", p->interp);
-    for (int i = 0; i < 2; i++)
-        if (p->reserved[i] != 0) return fail(WRLS_EINVAL, "reserved fields must be zero");
+    if (!(p->sigma0 >= 0.0f))
+        return fail(WRLS_EINVAL, "sigma0 = %g must be >= 0 (0: fixed lambda)", (double)p->sigma0);
+    if (p->sigma0 > 0.0f && !(p->lambda_min > 0.0f && p->lambda_min <= p->lambda))
+        return fail(WRLS_EINVAL, "lambda_min = %g outside (0, lambda = %g]", (double)p->lambda_min,
+                    (double)p->lambda);
     // The kernels address every array with 32-bit byte offsets; the state
     // copy is the largest array of a stream.
     const uint64_t copy = (uint64_t)stream_state_floats(p) * sizeof(float) *
@@ -322,6 +325,9 @@ wrls_status frame_args(const wrls_stream *s, const void *color, const void *feat
     a->pitch = s->pitch;
     a->lambda = p.lambda;
     a->inv_lambda = 1.0f / p.lambda;
+    a->auto_lambda = p.sigma0 > 0.0f;
+    a->inv_sigma0 = a->auto_lambda ? 1.0f / p.sigma0 : 0.0f;  // 0 for sigma0 = +inf
+    a->lambda_min = a->auto_lambda ? p.lambda_min : p.lambda;
     a->p0 = 1.0f / p.delta;
     a->var_floor = p.var_floor;
     a->fresh = s->frames == 0;

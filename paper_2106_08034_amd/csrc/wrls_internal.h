@@ -92,6 +92,9 @@ struct FrameArgs {
     int64_t pitch;          // pixel slots of a state copy (layout above)
     float lambda, inv_lambda, p0, var_floor;
     float alpha, inv_h2, eps;  // paper mode: Eq. 12 history weight, 1/h^2 and eps of Eq. 13
+    float inv_sigma0;       // automatic forgetting factor: 1 / the prescribed information
+    float lambda_min;       // automatic forgetting factor: lower limit (lambda is the upper)
+    int32_t auto_lambda;    // 1: forgetting factor chosen per pixel and step
     int32_t fresh;          // 1: no history (first frame)
     int32_t unit_weight;    // 1: w = 1 (plain RLS)
     int32_t nearest;        // 1: nearest reprojection

@@ -232,13 +232,41 @@ __device__ __forceinline__ void init_model(float p0, float *P, float *B)
     for (int k = 0; k < 3 * D; k++) B[k] = 0.0f;
 }
 
+// Automatic forgetting factor (the paper leaves its selection to future
+// work, Sec. 7.6), after Fortescue, Kershenbaum and Ydstie (Automatica,
+// 1981): lambda keeps the weighted a-posteriori error information of the
+// fit at a prescribed Sigma0.  With the forgetting of Eq. 10-11 that
+// information obeys V(t) = lambda V(t-1) + w sum_c e_c^2 lambda / (lambda +
+// w s) (e_c the a-priori residual of Eq. 8, s = p P p^T), so V(t) = Sigma0
+// is the quadratic lambda^2 + B lambda - a = 0 with a = w s and
+// B = w sum_c e_c^2 / Sigma0 + a - 1.  Its positive root, in (0, 1], is
+// taken in the cancellation-free form for either sign of B and limited to
+// [lambda_min, lambda].  A sample without weight leaves lambda at its upper
+// limit (root 1); overflow drives it to the lower one.
+__device__ __forceinline__ float forgetting_factor(const FrameArgs &a, float w, float s, bool ok,
+                                                   const float (&yc)[3], const float (&pred)[3])
+{
+    float lam = 1.0f;
+    if (ok) {
+        const float e0 = yc[0] - pred[0], e1 = yc[1] - pred[1], e2 = yc[2] - pred[2];
+        const float ws = w * s;
+        const float wb = w * fmaf(e2, e2, fmaf(e1, e1, e0 * e0));
+        const float B = fmaf(wb, a.inv_sigma0, ws - 1.0f);
+        const float r = sqrtf(fmaf(B, B, 4.0f * ws));
+        lam = B >= 0.0f ? (2.0f * ws) / (B + r) : 0.5f * (r - B);
+    }
+    // fmaxf returns the limit for a NaN root (inf / inf)
+    return fminf(fmaxf(lam, a.lambda_min), a.lambda);
+}
+
 // One weighted RLS update in place (Sec. 5.2-5.3) of the packed P and of B
 // (3 rows of D) with predictor p, colour yc and weight w (ok: the sample is
-// usable); out receives the a-posteriori prediction.
+// usable); out receives the a-posteriori prediction.  The forgetting factor
+// is the frame's lambda, or chosen per pixel (forgetting_factor).
 template <int D>
 __device__ __forceinline__ void rls_update(float *P, float *B, const float (&p)[D],
-                                           const float (&yc)[3], float w, bool ok, float lambda,
-                                           float inv_lambda, float (&out)[3])
+                                           const float (&yc)[3], float w, bool ok,
+                                           const FrameArgs &a, float (&out)[3])
 {
     // Gain (Eq. 14, multiplied through by w): k = P p^T, s = p k,
     // q = g k with g = w / (lambda + w s); g = 0 when w = 0.
@@ -254,16 +282,27 @@ __device__ __forceinline__ void rls_update(float *P, float *B, const float (&p)[
     float s = 0.0f;
 #pragma unroll
     for (int i = 0; i < D; i++) s = fmaf(p[i], kv[i], s);
+    // a-priori predictions p beta_c^T(t-1), for the residuals of Eq. 8
+    float pred[3];
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int i = 0; i < D; i++) acc = fmaf(p[i], B[c * D + i], acc);
+        pred[c] = acc;
+    }
+    float lambda = a.lambda, inv_lambda = a.inv_lambda;
+    if (a.auto_lambda) {
+        lambda = forgetting_factor(a, w, s, ok, yc, pred);
+        inv_lambda = 1.0f / lambda;
+    }
     const float g = w / fmaf(w, s, lambda);
 
     // Residual against the previous coefficients (Eq. 8) and update (Eq. 9),
     // then the a-posteriori prediction (Eq. 6).
 #pragma unroll
     for (int c = 0; c < 3; c++) {
-        float pred = 0.0f;
-#pragma unroll
-        for (int i = 0; i < D; i++) pred = fmaf(p[i], B[c * D + i], pred);
-        const float ge = ok ? g * (yc[c] - pred) : 0.0f;
+        const float ge = ok ? g * (yc[c] - pred[c]) : 0.0f;
         float post = 0.0f;
 #pragma unroll
         for (int i = 0; i < D; i++) {
@@ -356,7 +395,7 @@ __device__ __forceinline__ void update_pixel(const FrameArgs &a, int x, int y)
         for (int i = 1; i < D; i++) p[i] = finite(p[i]) ? p[i] : 0.0f;
     }
     float out[3];
-    rls_update<D>(st + p_entry0(D), st + beta_entry0(D), p, yc, w, ok, a.lambda, a.inv_lambda, out);
+    rls_update<D>(st + p_entry0(D), st + beta_entry0(D), p, yc, w, ok, a, out);
     store_pixel<NS>(a, j, n, st, out);
 }
 
@@ -432,7 +471,7 @@ __device__ __forceinline__ void update_pixel_paper(const FrameArgs &a, int x, in
     }
     const float p[D] = {1.0f, z[0], z[1], z[2]};
     float out[3];
-    rls_update<D>(st + p_entry0(D), st + beta_entry0(D), p, yc, w, ok, a.lambda, a.inv_lambda, out);
+    rls_update<D>(st + p_entry0(D), st + beta_entry0(D), p, yc, w, ok, a, out);
 #pragma unroll
     for (int c = 0; c < 3; c++) st[NM + c] = z[c];
     store_pixel<NS>(a, j, n, st, out);

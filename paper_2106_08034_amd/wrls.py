@@ -37,7 +37,7 @@ class wrls_params(ctypes.Structure):
                 ("var_floor", ctypes.c_float), ("in_dtype", ctypes.c_int32),
                 ("weight_mode", ctypes.c_int32), ("interp", ctypes.c_int32),
                 ("alpha", ctypes.c_float), ("h", ctypes.c_float), ("eps", ctypes.c_float),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("sigma0", ctypes.c_float), ("lambda_min", ctypes.c_float)]
 
 
 class wrls_frame(ctypes.Structure):
@@ -270,11 +270,12 @@ _INTERPS = {"bilinear": WRLS_INTERP_BILINEAR, "nearest": WRLS_INTERP_NEAREST}
 
 def make_params(width, height, d, lam=0.98, delta=1.0, var_floor=1e-6, in_dtype="f32",
                 weight_mode="invvar", interp="bilinear", alpha=0.75, h=0.75,
-                eps=1e-4) -> wrls_params:
+                eps=1e-4, sigma0=0.0, lam_min=0.0) -> wrls_params:
     p = wrls_params_default(width, height, d)
     p.lambda_, p.delta, p.var_floor = lam, delta, var_floor
     p.in_dtype, p.weight_mode, p.interp = _DTYPES[in_dtype], _WMODES[weight_mode], _INTERPS[interp]
     p.alpha, p.h, p.eps = alpha, h, eps
+    p.sigma0, p.lambda_min = sigma0, lam_min
     return p
 
 
@@ -290,15 +291,16 @@ class Stream:
                  var_floor: float = 1e-6, in_dtype: str = "f32", weight_mode: str = "invvar",
                  interp: str = "bilinear", hip_stream: Optional[int] = None,
                  device_mem: Optional[Tuple[int, int]] = None, alpha: float = 0.75,
-                 h: float = 0.75, eps: float = 1e-4):
+                 h: float = 0.75, eps: float = 1e-4, sigma0: float = 0.0, lam_min: float = 0.0):
         """device_mem: (pointer, bytes) of caller-owned device memory for the
         state (wrls_create_stream_in); None: the library allocates.
         weight_mode "paper" (d = 4): the paper's predictor and weight
-        (alpha, h, eps); features and variance are then not used."""
+        (alpha, h, eps); features and variance are then not used.
+        sigma0 > 0: automatic forgetting factor in [lam_min, lam]."""
         import torch
         self._torch = torch
         p = make_params(width, height, d, lam, delta, var_floor, in_dtype, weight_mode, interp,
-                        alpha, h, eps)
+                        alpha, h, eps, sigma0, lam_min)
         self.paper = weight_mode == "paper"
         self.params = p
         self.W, self.H, self.d = width, height, d

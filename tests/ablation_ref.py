@@ -1,7 +1,9 @@
 """The ablation of Sec. 5.3's design choices computed with the FP64 oracle:
 plain RLS (w = 1) against weighted RLS, with supplied features and with the
 paper's temporal feature, each with and without the 5x5 blend, scored by
-PSNR against the clean frames of a seeded c2-scene sequence."""
+PSNR against the clean frames of a seeded c2-scene sequence; and the fixed
+against the automatic forgetting factor on scenes with and without
+appearance edits."""
 from __future__ import annotations
 
 import math
@@ -47,4 +49,27 @@ def run(width: int, height: int, frames: int, warm: int):
                 se_t.append(np.mean((out - f.clean) ** 2))
                 se_b.append(np.mean((bl - f.clean) ** 2))
         res[name] = {"psnr_db": psnr(float(np.mean(se_t))), "psnr_blend_db": psnr(float(np.mean(se_b)))}
+    return res
+
+
+# automatic forgetting factor of the ablation: information and lower limit
+# (the upper limit is the fixed factor, 0.98)
+AUTO_SIGMA0, AUTO_LAM_MIN = 60.0, 0.5
+
+
+def run_forgetting(scene: str, width: int, height: int, frames: int, warm: int, edit: int):
+    """PSNR of weighted RLS with supplied features, fixed lambda = 0.98
+    against the automatic factor, over frames warm..end and over edit..end
+    (the c3 scene's colour LUT changes at frame 15 and its light at 22; the
+    c2 scene has no edit)."""
+    wl = (synth.c3 if scene == "c3" else synth.c2)(width=width, height=height, frames=frames)
+    src = synth.FrameSource(wl)
+    seq = [src.next() for _ in range(frames)]
+    delta = math.exp(-synth.VAR_MU)
+    res = {}
+    for name, kw in (("fixed", {}), ("auto", dict(sigma0=AUTO_SIGMA0, lam_min=AUTO_LAM_MIN))):
+        o = oracle.Oracle(width, height, wl.d, lam=0.98, delta=delta, **kw)
+        se = [np.mean((o.step(f.color, f.feats, f.var, f.motion) - f.clean) ** 2) for f in seq]
+        res[name] = {"psnr_db": psnr(float(np.mean(se[warm:]))),
+                     "psnr_after_edit_db": psnr(float(np.mean(se[edit:])))}
     return res

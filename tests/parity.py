@@ -133,20 +133,24 @@ class Pair:
     predictor of the error measures is then [1, z] with the oracle's z."""
 
     def __init__(self, W, H, d, lam=0.98, delta=1.0, var_floor=1e-6, in_dtype="f32",
-                 weight_mode="invvar", interp="bilinear", alpha=0.75, h=0.75, eps=1e-4):
+                 weight_mode="invvar", interp="bilinear", alpha=0.75, h=0.75, eps=1e-4,
+                 sigma0=0.0, lam_min=0.0):
         import oracle
         from paper_2106_08034_amd import wrls
         # both sides take the binary32 values of the paper-mode constants
         alpha, h, eps = (float(np.float32(v)) for v in (alpha, h, eps))
+        # and those of the forgetting factor's limits and information
+        lam, sigma0, lam_min = (float(np.float32(v)) for v in (lam, sigma0, lam_min))
         self.gpu = wrls.Stream(W, H, d, lam=lam, delta=delta, var_floor=var_floor,
                                in_dtype=in_dtype, weight_mode=weight_mode, interp=interp,
-                               alpha=alpha, h=h, eps=eps)
+                               alpha=alpha, h=h, eps=eps, sigma0=sigma0, lam_min=lam_min)
         self.ref = oracle.Oracle(W, H, d, lam=lam, delta=delta, var_floor=var_floor,
                                  wmode={"invvar": oracle.W_INVVAR, "one": oracle.W_ONE,
                                         "paper": oracle.W_PAPER}[weight_mode],
                                  interp={"bilinear": oracle.INTERP_BILINEAR,
                                          "nearest": oracle.INTERP_NEAREST}[interp],
-                                 alpha=alpha, h_bw=h, eps=eps)
+                                 alpha=alpha, h_bw=h, eps=eps, sigma0=sigma0,
+                                 lam_min=lam_min if sigma0 > 0 else None)
         self.d = d
         self.paper = weight_mode == "paper"
         self.alpha = alpha

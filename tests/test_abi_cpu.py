@@ -116,10 +116,19 @@ def test_paper_mode_parameters():
     assert L.wrls_set_history(None, None) == wrls.WRLS_EINVAL
 
 
-def test_reserved_must_be_zero():
+def test_automatic_forgetting_parameters():
+    """sigma0 = 0 (the default) fixes lambda; sigma0 > 0 or +inf turns the
+    automatic factor on and needs lambda_min in (0, lambda]."""
     p = wrls.wrls_params_default(8, 8, 8)
-    p.reserved[1] = 1
-    assert wrls.wrls_params_validate(p) == wrls.WRLS_EINVAL
+    assert p.sigma0 == 0.0 and p.lambda_min == 0.0
+    assert wrls.wrls_params_validate(p) == wrls.WRLS_OK
+    for s0, lo, ok in ((30.0, 0.5, True), (float("inf"), 0.98, True), (30.0, 0.0, False),
+                       (30.0, 0.99, False), (-1.0, 0.5, False), (float("nan"), 0.5, False),
+                       (30.0, float("nan"), False)):
+        q = wrls.wrls_params_default(8, 8, 8)
+        q.sigma0, q.lambda_min = s0, lo
+        rc = wrls.wrls_params_validate(q)
+        assert (rc == wrls.WRLS_OK) == ok, (s0, lo, wrls.wrls_last_error())
 
 
 def test_null_arguments():

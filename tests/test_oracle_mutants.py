@@ -38,6 +38,15 @@ MUTANTS = {
     "output_a_priori": ("        out[c] = acc;\n", "        out[c] = prior_out ? prior_out[c] : acc;\n"),
     "features_reversed": ("p[i] = feats[(size_t)(i - 1) * n + j];", "p[i] = feats[(size_t)(d - 1 - i) * n + j];"),
     "outlier_not_skipped": ("    if (!isfinite(var) || var < 0.0) return 0.0;\n", ""),
+    # automatic forgetting factor (Fortescue, Kershenbaum and Ydstie)
+    "vff_root_sign": ("lam = (-B + sqrt(B * B + 4.0 * a)) / 2.0;", "lam = (B + sqrt(B * B + 4.0 * a)) / 2.0;"),
+    "vff_error_unweighted": ("double a = w * s, b = w * e2;", "double a = w * s, b = e2;"),
+    "vff_gain_term_dropped": ("double B = b / o->sigma0 + a - 1.0;", "double B = b / o->sigma0 - 1.0;"),
+    "vff_sigma0_inverted": ("double B = b / o->sigma0 + a - 1.0;", "double B = b * o->sigma0 + a - 1.0;"),
+    "vff_upper_limit_ignored": ("    if (lam > o->lambda) lam = o->lambda;\n", ""),
+    "vff_lower_limit_ignored": ("    if (lam < o->lambda_min) lam = o->lambda_min;\n", ""),
+    "vff_factor_not_applied": ("double lambda = forgetting_factor(o, w, pPpt, y, pred_prior);",
+                               "double lambda = o->lambda; (void)forgetting_factor(o, w, pPpt, y, pred_prior);"),
     # paper mode (Eq. 12-13)
     "eq12_alpha_swapped": ("z[c] = o->alpha * psi + (1.0 - o->alpha) * yc[c];",
                            "z[c] = (1.0 - o->alpha) * psi + o->alpha * yc[c];"),
@@ -87,6 +96,7 @@ def test_pins_catch_planted_mistake(name, tmp_path):
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_pins.py"),
                         os.path.join(ROOT, "tests", "test_oracle_paper_pins.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_forgetting_pins.py"),
                         os.path.join(ROOT, "tests", "test_oracle_blend_pins.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=300)
     assert r.returncode != 0, "planted mistake %r passed every pin:\n%s" % (name, r.stdout[-2000:])
