@@ -1,12 +1,22 @@
 #!/usr/bin/env python3
 """Throughput of the wRLS temporal denoiser on one MI355X.
 
-Default workload: 1920x1080, 60 frames, 2.3 px/frame sub-pixel pan with a
-5% disocclusion mask, d = 8 predictors [1, albedo, normal, depth], FP32
-inputs and state, lambda = 0.98, heteroscedastic lognormal noise variance.
-All frames are generated (seeded, synthetic) and uploaded to HBM before the
-timed region; one step denoises one frame through the C ABI (one kernel
-launch).  Prints one JSON line.
+Default workload (the headline): 3840x2160, 30 frames of a camera orbiting
+a pivot (per-pixel motion from a seeded depth map), a colour-LUT edit at
+frame 15 and a light change at frame 22, d = 10 predictors, FP16 colour and
+features, FP32 state, lambda = 0.98, heteroscedastic lognormal noise
+variance.  All frames are generated (seeded, synthetic) and uploaded to HBM
+before the timed region; one step denoises one frame through the C ABI (one
+kernel launch).  Beside the headline the default run also reports:
+  parity        the error of a GPU pass from frame 0 against the FP64 oracle's
+                outputs of the same frames (the CPU baseline's first pass),
+                and against an oracle fed the unrounded FP32 inputs;
+  c2            the 1920x1080 d = 8 FP32 pan, with its roofline and parity;
+  c4_batched    16 mixed-resolution streams: one batched launch per round
+                against 16 per-stream launches;
+  serving       32 sessions served with continuous batching against one
+                launch per frame, at the trace's load and at a saturating one.
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -14,6 +24,7 @@ import argparse
 import hashlib
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -21,6 +32,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, AMD published peak
+# MI355X FP32 vector peaks: 157.3 TFLOP/s with packed FP32 instructions,
+# which the library's build disables, so 78.6 TFLOP/s is the reachable one.
+FP32_VECTOR_PEAK_TFLOPS = 78.6
+FP32_PACKED_PEAK_TFLOPS = 157.3
+METRIC = "denoised Mpix/s (wRLS step) + % HBM roofline; p99 frame latency @32 streams"
+DATA = "synthetic (seeded procedural scene, lognormal per-pixel noise variance)"
 
 
 def algorithmic_bytes_per_pixel(d: int, in_bytes: int, motion: bool = True) -> int:
@@ -50,9 +67,6 @@ def blend_bytes_per_pixel(d: int, in_bytes: int, paper: bool = False) -> int:
     of neighbouring tiles are cache hits and are not counted."""
     pred = 12 if paper else (d - 1) * in_bytes
     return 3 * d * 4 + pred + 12 + 12
-
-
-FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector peak (packed FMA); non-packed: 78.6
 
 
 def blend_flop_per_pixel(d: int) -> int:
@@ -112,6 +126,18 @@ def load_traffic(workload: str, kernel: str = ""):
     return rec.get("hbm_bytes_per_launch")
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (lscpu), for the CPU baseline."""
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return "unknown"
+
+
 def make_workload(name: str):
     import synth
     if name == "c2":
@@ -134,7 +160,9 @@ def ablation_modes(d_features: int):
     equals scaling delta by 1/c), so delta is given in each mode's weight
     units: one unit-weight sample for w = 1 and for the Eq. 13 weight (at
     most 1), one median-weight sample (1 / median variance) for inverse
-    variance weights.  A very large h makes the Eq. 13 weight 1 everywhere."""
+    variance weights.  A very large h makes the Eq. 13 weight 1 everywhere.
+    The last mode adds the automatic forgetting factor (sigma0 60, lambda in
+    [0.5, 0.98]) to weighted RLS."""
     import math
     import synth
     return [
@@ -142,22 +170,25 @@ def ablation_modes(d_features: int):
         ("wrls_features", dict(d=d_features, weight_mode="invvar", delta=math.exp(-synth.VAR_MU))),
         ("rls_temporal_feature", dict(d=4, weight_mode="paper", h=1e3)),
         ("wrls_temporal_feature", dict(d=4, weight_mode="paper")),
+        ("wrls_features_auto_lambda", dict(d=d_features, weight_mode="invvar",
+                                           delta=math.exp(-synth.VAR_MU), sigma0=60.0, lam_min=0.5)),
     ]
 
 
 def run_ablation(width: int, height: int, frames: int, warm: int, sigma_s: float = 1.5,
-                 sigma_r: float = 0.15, sweep=(0.05, 0.15, 0.5, float("inf"))):
+                 sigma_r: float = 0.15, sweep=(0.05, 0.15, 0.5, float("inf")), scene: str = "c2"):
     """PSNR (peak 1, linear) against the clean frames, over frames warm..end,
     of the temporal output and of the spatially blended output of every
     ablation mode, on the c2 scene (sub-pixel pan, disocclusions,
-    heteroscedastic 1-spp noise) at the given size; also the temporal
-    flicker, the RMS frame-to-frame change of the error.  Everything runs
-    through libwrls on the GPU."""
+    heteroscedastic 1-spp noise) or the c3 scene (orbit, colour-LUT edit at
+    frame 15, light change at 22; d = 10, FP16 inputs) at the given size;
+    also the temporal flicker, the RMS frame-to-frame change of the error.
+    Everything runs through libwrls on the GPU."""
     import math
     import torch
     import synth
     from paper_2106_08034_amd import wrls
-    wl = synth.c2(width=width, height=height, frames=frames)
+    wl = (synth.c3 if scene == "c3" else synth.c2)(width=width, height=height, frames=frames)
     src = synth.FrameSource(wl)
     dev = torch.device("cuda:0")
     up = lambda a: torch.from_numpy(a).to(dev)
@@ -169,12 +200,12 @@ def run_ablation(width: int, height: int, frames: int, warm: int, sigma_s: float
     def psnr(mse):
         return round(10.0 * math.log10(1.0 / mse), 3)
 
-    res = {"input": {"psnr_db": psnr(float(sum(((c - cl) ** 2).mean().item()
+    res = {"input": {"psnr_db": psnr(float(sum(((c.float() - cl) ** 2).mean().item()
                                                    for c, _, _, _, cl in seq[warm:]) / (frames - warm)))}}
     for name, kw in ablation_modes(wl.d):
         d = kw.pop("d")
-        st = wrls.Stream(width, height, d, **kw)
         paper = kw["weight_mode"] == "paper"
+        st = wrls.Stream(width, height, d, in_dtype=wl.in_dtype, **kw)
         sigmas = [(sigma_s, sigma_r)] + ([(sigma_s, r) for r in sweep] if name == "wrls_features" else [])
         se_t, se_b = 0.0, [0.0] * len(sigmas)
         fl_t, fl_b, prev_t, prev_b = 0.0, 0.0, None, None
@@ -202,39 +233,67 @@ def run_ablation(width: int, height: int, frames: int, warm: int, sigma_s: float
     return res
 
 
-def bench_serving(args):
+def _frame_pools(torch, shapes, count):
+    """Device frames of the serving recipe, `count` per (width, height)."""
+    import synth
+    pools = {}
+    for i, (w, h) in enumerate(shapes):
+        src = synth.FrameSource(synth.c5_frame_pool(w, h, count), stream=i)
+        pools[(w, h)] = [tuple(torch.from_numpy(a).cuda() for a in (f.color, f.feats, f.var, f.motion))
+                         for f in (src.next() for _ in range(count))]
+    torch.cuda.synchronize()
+    return pools
+
+
+def bench_serving(args, modes=("batched", "per_stream"), saturating=True):
     """32 sessions (Poisson 4/s arrivals, Exp(20 s) durations, 720p..4K,
     30..60 Hz, FP16, d = 8) served in real time for args.serve_seconds:
-    HBM-budget admission, continuous batching, two steps in flight.
-    Returns the server's report (Mpix/s, p50/p99 latency, ...)."""
+    HBM-budget admission, continuous batching with two steps in flight, or
+    the per-stream baseline (one launch per frame).  With `saturating`, the
+    same sessions again at 16 arrivals/s and 120-240 Hz (more pixels per
+    second than the GPU steps) for args.saturating_seconds.  Returns
+    {trace: {mode: report}} (Mpix/s, p50/p99 latency, ...)."""
     import torch
 
     import synth
-    from paper_2106_08034_amd.serve import Server
+    from paper_2106_08034_amd.serve import SATURATING, Server
 
-    sessions = synth.c5_sessions()
     t0 = time.time()
-    pools = {}
-    for i, (w, h) in enumerate(synth.C5_RESOLUTIONS):
-        src = synth.FrameSource(synth.c5_frame_pool(w, h, args.pool), stream=i)
-        pools[(w, h)] = [tuple(torch.from_numpy(a).cuda() for a in (f.color, f.feats, f.var, f.motion))
-                         for f in (src.next() for _ in range(args.pool))]
-    torch.cuda.synchronize()
+    pools = _frame_pools(torch, synth.C5_RESOLUTIONS, args.pool)
     print("serving: generated %d frames per resolution in %.1fs" % (args.pool, time.time() - t0),
           file=sys.stderr, flush=True)
     budget = int((args.budget_gb or 200.0) * (1 << 30))
-    srv = Server(budget_bytes=budget, max_batch=32)
-    res, _ = srv.run(sessions, pools, seconds=args.serve_seconds)
-    res["budget_gb"] = round(budget / (1 << 30), 2)
-    res["frames_cycled_per_resolution"] = args.pool
-    return res
+    traces = [("c5", synth.c5_sessions(), args.serve_seconds)]
+    if saturating:
+        traces.append(("c5_saturating", synth.c5_sessions(**SATURATING), args.saturating_seconds))
+    out = {}
+    for name, sessions, seconds in traces:
+        out[name] = {}
+        for mode in modes:
+            srv = Server(budget_bytes=budget, max_batch=32, per_stream=mode == "per_stream",
+                         tile=tuple(args.serve_tile))
+            res, _ = srv.run(sessions, pools, seconds=seconds)
+            res["budget_gb"] = round(budget / (1 << 30), 2)
+            res["frames_cycled_per_resolution"] = args.pool
+            out[name][mode] = res
+            print("serving %s %s: %.0f Mpix/s, p50 %.3f ms, p99 %.3f ms" % (
+                name, mode, res["mpix_per_s"], res["p50_ms"], res["p99_ms"]), file=sys.stderr, flush=True)
+            del srv
+            torch.cuda.synchronize()
+    if "batched" in modes and "per_stream" in modes:
+        for name in out:
+            b, s = out[name]["batched"], out[name]["per_stream"]
+            out[name]["batched_over_per_stream"] = {
+                "mpix_per_s": round(b["mpix_per_s"] / max(s["mpix_per_s"], 1e-9), 3),
+                "p99_ms": round(b["p99_ms"] / max(s["p99_ms"], 1e-9), 3)}
+    return out
 
 
-def bench_batched(args):
+def bench_batched(args, tune: bool, small: bool = True):
     """16 streams of mixed resolution (640x480 .. 2560x1440), FP16 inputs,
-    d = 8: one persistent batched launch per round (HIP graph replay) against
-    16 per-stream launches per round on the same HIP stream."""
-    import numpy as np
+    d = 8: one batched launch per round (HIP graph replay) against 16
+    per-stream launches per round on the same HIP stream; with `small`, the
+    same for 64 streams of 320x240, where launch overhead dominates."""
     import torch
 
     import synth
@@ -250,18 +309,22 @@ def bench_batched(args):
     torch.cuda.synchronize()
     print("generated %d frames for %d streams in %.1fs" % (args.pool * len(wls), len(wls),
                                                           time.time() - t0), file=sys.stderr, flush=True)
-    from paper_2106_08034_amd import autotune
-    shapes = [(wl.width, wl.height) for wl in wls]
-    best, tune_ms = autotune.tune_batch(shapes, 8, pools, "f16", cache=autotune.TuneCache(None),
-                                        force=True)
-    print("autotuned batch launch shape %s" % (best,), file=sys.stderr, flush=True)
+    tune_ms = None
+    if tune:
+        from paper_2106_08034_amd import autotune
+        shapes = [(wl.width, wl.height) for wl in wls]
+        best, tune_ms = autotune.tune_batch(shapes, 8, pools, "f16", cache=autotune.TuneCache(None),
+                                            force=True)
+        print("autotuned batch launch shape %s" % (best,), file=sys.stderr, flush=True)
+    else:
+        best = tuple(args.batch_tile)
     batch = wrls.Batch(len(wls), 8, "f16")
     batch.set_tile(*best)
     hs = batch.hip_stream
     ext = torch.cuda.ExternalStream(hs)
     mixed = [wrls.Stream(wl.width, wl.height, 8, in_dtype="f16", hip_stream=hs) for wl in wls]
     single = [wrls.Stream(wl.width, wl.height, 8, in_dtype="f16", hip_stream=hs) for wl in wls]
-    for s in single:  # the per-stream baseline gets the same tuned tile
+    for s in single:  # the per-stream baseline gets the same tile
         s.set_tile(best[0], best[1], 0)
     outs = [torch.empty((3, wl.height, wl.width), device="cuda") for wl in wls]
     npix = sum(wl.width * wl.height for wl in wls)
@@ -289,88 +352,338 @@ def bench_batched(args):
             torch.cuda.synchronize()
             wall = time.perf_counter() - t_start
         res[name] = {"ms_per_round": e0.elapsed_time(e1) / K, "wall_ms_per_round": wall * 1e3 / K}
-    # where launches dominate: 64 small streams (320x240, same recipe)
-    small = [synth.Workload(name="small-%02d" % i, width=320, height=240, frames=args.pool, d=8,
-                            in_dtype="f16", motion="pan", pan=(2.3, 0.0), disocclusion=0.05,
-                            config_index=3) for i in range(64)]
-    spools = []
-    for i, wl in enumerate(small):
-        src = synth.FrameSource(wl, stream=i)
-        spools.append([tuple(torch.from_numpy(a).cuda() for a in (f.color, f.feats, f.var, f.motion))
-                       for f in (src.next() for _ in range(2))])
-    sb = wrls.Batch(len(small), 8, "f16")
-    sm = [wrls.Stream(wl.width, wl.height, 8, in_dtype="f16", hip_stream=sb.hip_stream) for wl in small]
-    ss = [wrls.Stream(wl.width, wl.height, 8, in_dtype="f16", hip_stream=sb.hip_stream) for wl in small]
-    souts = [torch.empty((3, wl.height, wl.width), device="cuda") for wl in small]
-    sext = torch.cuda.ExternalStream(sb.hip_stream)
-    small_res = {}
-    for name, fn in (("batched_graph", lambda i: sb.step(sm, [p[i % 2] for p in spools], souts)),
-                     ("per_stream_launches",
-                      lambda i: [s.step(*p[i % 2], out=o) for s, p, o in zip(ss, spools, souts)])):
-        with torch.cuda.stream(sext):
-            for i in range(W):
-                fn(i)
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(sext)
-            for i in range(K):
-                fn(W + i)
-            e1.record(sext)
-            torch.cuda.synchronize()
-        small_res[name] = e0.elapsed_time(e1) / K
+    small_res = None
+    if small:
+        sm_wl = [synth.Workload(name="small-%02d" % i, width=320, height=240, frames=args.pool, d=8,
+                                in_dtype="f16", motion="pan", pan=(2.3, 0.0), disocclusion=0.05,
+                                config_index=3) for i in range(64)]
+        spools = []
+        for i, wl in enumerate(sm_wl):
+            src = synth.FrameSource(wl, stream=i)
+            spools.append([tuple(torch.from_numpy(a).cuda() for a in (f.color, f.feats, f.var, f.motion))
+                           for f in (src.next() for _ in range(2))])
+        sb = wrls.Batch(len(sm_wl), 8, "f16")
+        sm = [wrls.Stream(wl.width, wl.height, 8, in_dtype="f16", hip_stream=sb.hip_stream) for wl in sm_wl]
+        ss = [wrls.Stream(wl.width, wl.height, 8, in_dtype="f16", hip_stream=sb.hip_stream) for wl in sm_wl]
+        souts = [torch.empty((3, wl.height, wl.width), device="cuda") for wl in sm_wl]
+        sext = torch.cuda.ExternalStream(sb.hip_stream)
+        small_res = {}
+        for name, fn in (("batched_graph", lambda i: sb.step(sm, [p[i % 2] for p in spools], souts)),
+                         ("per_stream_launches",
+                          lambda i: [s.step(*p[i % 2], out=o) for s, p, o in zip(ss, spools, souts)])):
+            with torch.cuda.stream(sext):
+                for i in range(W):
+                    fn(i)
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(sext)
+                for i in range(K):
+                    fn(W + i)
+                e1.record(sext)
+                torch.cuda.synchronize()
+            small_res[name] = round(e0.elapsed_time(e1) / K, 4)
+        small_res["batched_speedup"] = round(small_res["per_stream_launches"] / small_res["batched_graph"], 3)
     bpp = algorithmic_bytes_per_pixel(8, 2)
     b_ms = res["batched_graph"]["ms_per_round"]
     s_ms = res["per_stream_launches"]["ms_per_round"]
     gbs = bpp * npix / (b_ms / 1e3) / 1e9
     return {
-        "metric": "denoised Mpix/s (wRLS step, batched) + % HBM roofline",
-        "value": round(npix / (b_ms / 1e3) / 1e6, 2), "unit": "Mpix/s", "n_gpus": 1,
-        "steps": K, "warmup": W, "ms_per_step": round(b_ms, 4), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32 (f16 inputs)",
-        "data": "synthetic (seeded procedural scene, lognormal per-pixel noise variance)",
-        "config": {"workload": "c4-16-streams-mixed-640x480..2560x1440-d8-f16",
-                   "streams": len(wls), "pixels_per_round": npix,
-                   "resolutions": ["%dx%d" % (wl.width, wl.height) for wl in wls],
-                   "frames_cycled_per_stream": args.pool,
-                   "autotuned": {"tile_w_log2": best[0], "block_threads": best[1],
-                                 "blocks_per_cu": best[2],
-                                 "candidates_ms": {k: round(v, 4) for k, v in tune_ms.items()}}},
-        "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "wrls batch_kernel<8, f16>", "algorithmic_bytes_per_pixel": bpp},
+        "workload": "c4-16-streams-mixed-640x480..2560x1440-d8-f16",
+        "streams": len(wls), "pixels_per_round": npix,
+        "resolutions": ["%dx%d" % (wl.width, wl.height) for wl in wls],
+        "frames_cycled_per_stream": args.pool,
+        "launch_shape": {"tile_w_log2": best[0], "block_threads": best[1], "blocks_per_cu": best[2],
+                         "autotuned": tune,
+                         "candidates_ms": ({k: round(v, 4) for k, v in tune_ms.items()}
+                                           if tune_ms else None)},
+        "batched": {"ms_per_round": round(b_ms, 4), "value": round(npix / (b_ms / 1e3) / 1e6, 2),
+                    "unit": "Mpix/s",
+                    "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                                 "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                                 "kernel": "wrls batch_kernel<8, f16>",
+                                 "algorithmic_bytes_per_pixel": bpp}},
         "per_stream_launches": {"ms_per_round": round(s_ms, 4),
-                                "value": round(npix / (s_ms / 1e3) / 1e6, 2),
-                                "batched_speedup": round(s_ms / b_ms, 4)},
+                                "value": round(npix / (s_ms / 1e3) / 1e6, 2), "unit": "Mpix/s"},
+        "batched_speedup": round(s_ms / b_ms, 4),
         "wall_ms_per_round": {k: round(v["wall_ms_per_round"], 4) for k, v in res.items()},
-        "small_frames_64x320x240": {k: round(v, 4) for k, v in small_res.items()} | {
-            "batched_speedup": round(small_res["per_stream_launches"] / small_res["batched_graph"], 3)},
-        "cpu_baseline": None,
+        "small_frames_64x320x240_ms_per_round": small_res,
     }
+
+
+class _Parity:
+    """Running error of GPU outputs against the oracle's, per frame:
+    G1 = max |gpu - ref| / max(|ref|, s, 1e-3 RMS(ref)) with s the magnitude
+    of the output's terms (the parity tests' gate, 1e-4), and the error with
+    |ref| alone as the denominator (floored at 1e-3 RMS).  Computed on the
+    GPU in float64."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.g1 = 0.0
+        self.y_rel = 0.0
+        self.frames = 0
+
+    def add(self, gpu_out, ref, scale):
+        torch = self.torch
+        r = torch.from_numpy(ref).cuda()
+        g = gpu_out.double()
+        tau = 1e-3 * float(torch.sqrt(torch.mean(r * r)))
+        diff = (g - r).abs()
+        den_y = torch.clamp(r.abs(), min=max(tau, 1e-30))
+        self.y_rel = max(self.y_rel, float((diff / den_y).max()))
+        if scale is not None:
+            den = torch.maximum(den_y, torch.from_numpy(scale).cuda())
+            self.g1 = max(self.g1, float((diff / den).max()))
+        self.frames += 1
+
+    def report(self):
+        return {"frames": self.frames, "g1_max": float("%.3g" % self.g1),
+                "y_relative_max": float("%.3g" % self.y_rel), "g1_bar": 1e-4,
+                "within_bar": self.g1 <= 1e-4}
+
+
+def bench_step(args, workload: str, with_cpu: bool, parity_frames=None, with_blend: bool = True):
+    """One per-frame workload through wrls_step: K timed steps over the
+    uploaded sequence, the roofline of the step kernel, the spatial blend,
+    and (with_cpu) the oracle timed on the host over the same frames, whose
+    outputs also give the parity of a GPU pass from frame 0; parity_frames
+    limits that pass (None: all frames of the oracle sample)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2106_08034_amd import wrls
+
+    wl = make_workload(workload)
+    paper = workload == "c2p"
+    d_model = 4 if paper else wl.d
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    src = synth.FrameSource(wl)
+    host_frames, dev_frames = [], []
+    n_unrounded = args.unrounded_frames if wl.in_dtype == "f16" else 0
+    up = lambda a: torch.from_numpy(a).to(dev)
+    for t in range(wl.frames):
+        f = src.next(keep_unrounded=t < n_unrounded)
+        host_frames.append(f)
+        if paper:  # features and variance are not inputs of paper mode
+            dev_frames.append((up(f.color), None, None, up(f.motion)))
+        else:
+            dev_frames.append(tuple(up(a) for a in (f.color, f.feats, f.var, f.motion)))
+    torch.cuda.synchronize()
+    print("generated and uploaded %d frames of %s in %.1fs" % (wl.frames, wl.name, time.time() - t0),
+          file=sys.stderr, flush=True)
+
+    stream = wrls.Stream(wl.width, wl.height, d_model, lam=0.98, in_dtype=wl.in_dtype,
+                         weight_mode="paper" if paper else "invvar")
+    out = torch.empty((3, wl.height, wl.width), dtype=torch.float32, device=dev)
+    cs = torch.cuda.current_stream()
+    for i in range(args.warmup):
+        stream.step(*dev_frames[i % wl.frames], out=out)
+    torch.cuda.synchronize()
+
+    K = args.steps
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    ev[0].record(cs)
+    for i in range(K):
+        stream.step(*dev_frames[(args.warmup + i) % wl.frames], out=out)
+        ev[i + 1].record(cs)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    per_launch_ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(K)]
+    total_ev_ms = ev[0].elapsed_time(ev[K])
+    npix = wl.width * wl.height
+    in_bytes = 2 if wl.in_dtype == "f16" else 4
+    if paper:
+        bpp = algorithmic_bytes_per_pixel_paper(in_bytes, motion=wl.motion != "static")
+    else:
+        bpp = algorithmic_bytes_per_pixel(wl.d, in_bytes, motion=wl.motion != "static")
+    avg_launch_s = float(np.mean(per_launch_ms)) / 1e3
+    achieved_gbs = bpp * npix / avg_launch_s / 1e9
+    copy_gbs = measure_copy_gbs(torch, wrls, bpp * npix)
+    res = {
+        "value": round(K * npix / elapsed / 1e6, 2), "unit": "Mpix/s",
+        "ms_per_step": round(elapsed * 1e3 / K, 4),
+        "dtype": "f32" if wl.in_dtype == "f32" else "f32 (f16 inputs)",
+        "config": {"workload": wl.name + ("-paper-mode-d4" if paper else ""),
+                   "width": wl.width, "height": wl.height, "d": d_model,
+                   "frames_in_sequence": wl.frames, "lambda": 0.98,
+                   "input_dtype": wl.in_dtype, "state_dtype": "f32"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
+                     "traffic": load_traffic(workload),
+                     "kernel": "wrls paper_step_kernel" if paper else "wrls step_kernel<%d>" % wl.d,
+                     "algorithmic_bytes_per_pixel": bpp,
+                     "avg_launch_us": round(avg_launch_s * 1e6, 2),
+                     "launch_us_min_max": [round(min(per_launch_ms) * 1e3, 2),
+                                           round(max(per_launch_ms) * 1e3, 2)],
+                     "event_total_ms": round(total_ev_ms, 3),
+                     "measured_copy": {"kernel": "wrls_device_copy, same bytes per launch",
+                                       "gbs": round(copy_gbs, 1),
+                                       "frac": round(achieved_gbs / copy_gbs, 4)}},
+    }
+
+    if with_blend:
+        # the spatial blend (a second kernel after the step), timed on its
+        # own over the last state: K launches, HIP events on the launch stream
+        f_last = dev_frames[(args.warmup + K - 1) % wl.frames][1]
+        fin = torch.empty_like(out)
+        ss, sr = args.blend_sigmas
+        stream.blend(f_last, out, ss, sr, out=fin)
+        torch.cuda.synchronize()
+        evb = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
+        evb[0].record(cs)
+        for i in range(K):
+            stream.blend(f_last, out, ss, sr, out=fin)
+            evb[i + 1].record(cs)
+        torch.cuda.synchronize()
+        blend_s = float(np.mean([evb[i].elapsed_time(evb[i + 1]) for i in range(K)])) / 1e3
+        bbpp = blend_bytes_per_pixel(d_model, in_bytes, paper)
+        bflop = blend_flop_per_pixel(d_model)
+        alu_tflops = bflop * npix / blend_s / 1e12
+        res["spatial_blend"] = {
+            "kernel": "wrls blend_kernel<%d>" % d_model, "sigma_s": ss, "sigma_r": sr,
+            "avg_launch_us": round(blend_s * 1e6, 2), "mpix_per_s": round(npix / blend_s / 1e6, 1),
+            "algorithmic_bytes_per_pixel": bbpp,
+            "achieved": round(bbpp * npix / blend_s / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(bbpp * npix / blend_s / 1e9 / HBM_PEAK_GBS, 4),
+            "traffic": load_traffic(workload, "blend"),
+            "step_plus_blend_mpix_per_s": round(npix / (avg_launch_s + blend_s) / 1e6, 1),
+            # the blend's arithmetic rate against the FP32 vector peak without
+            # packed instructions (the build's), and the packed peak's fraction
+            "alu": {"bound": "alu", "flop_per_pixel": bflop, "achieved": round(alu_tflops, 2),
+                    "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(alu_tflops / FP32_VECTOR_PEAK_TFLOPS, 4),
+                    "frac_of_packed_peak": round(alu_tflops / FP32_PACKED_PEAK_TFLOPS, 4)}}
+    stream.close()
+
+    if with_cpu or parity_frames:
+        # The oracle as it stands on the same frames.  Its first pass also
+        # gives the reference outputs of a GPU pass from frame 0 (a fresh
+        # stream), compared frame by frame; further passes until about 10 s
+        # of CPU work time it.
+        import oracle
+        n_cpu = args.cpu_frames or wl.frames
+        n_par = n_cpu if parity_frames is None else min(parity_frames, n_cpu)
+
+        def make_oracle():
+            if paper:
+                return oracle.Oracle(wl.width, wl.height, 4, lam=0.98, wmode=oracle.W_PAPER)
+            return oracle.Oracle(wl.width, wl.height, wl.d, lam=0.98)
+
+        def step_oracle(o, f, want_scale=False, unrounded=False):
+            c = f.color_f32 if unrounded else f.color
+            fe = f.feats_f32 if unrounded else f.feats
+            if paper:
+                return o.step(c, None, None, f.motion, want_scale=want_scale)
+            return o.step(c, fe, f.var, f.motion, want_scale=want_scale)
+
+        gpu = wrls.Stream(wl.width, wl.height, d_model, lam=0.98, in_dtype=wl.in_dtype,
+                          weight_mode="paper" if paper else "invvar")
+        par = _Parity(torch)
+        par32 = _Parity(torch)
+        o = make_oracle()
+        o32 = make_oracle() if n_unrounded else None
+        cpu_s = 0.0
+        for t, f in enumerate(host_frames[:n_cpu] if with_cpu else host_frames[:n_par]):
+            tc = time.perf_counter()
+            r = step_oracle(o, f, want_scale=t < n_par)
+            cpu_s += time.perf_counter() - tc
+            if t < n_par:
+                ref, scale = r
+                g = gpu.step(*dev_frames[t])
+                par.add(g, ref, scale)
+                if o32 is not None and t < n_unrounded:
+                    par32.add(g, step_oracle(o32, f, unrounded=True), None)
+        del o, o32
+        gpu.close()
+        p = par.report()
+        p["reference"] = "FP64 oracle on the same inputs (FP16-rounded where the workload is FP16)"
+        if n_unrounded:
+            p["vs_unrounded_fp32_inputs"] = {
+                "frames": par32.frames, "y_relative_max": float("%.3g" % par32.y_rel),
+                "note": "GPU on FP16 inputs against the oracle fed the unrounded FP32 inputs: "
+                        "measures the binary16 rounding of colour and features"}
+        res["parity"] = p
+        if with_cpu:
+            passes, frames_done = 1, n_cpu
+            while passes < 8 and cpu_s < 10.0:
+                o = make_oracle()
+                tc = time.perf_counter()
+                for f in host_frames[:n_cpu]:
+                    step_oracle(o, f)
+                cpu_s += time.perf_counter() - tc
+                del o
+                passes += 1
+                frames_done += n_cpu
+            cores = oracle.threads()
+            cpu = {"value": round(frames_done * npix / cpu_s / 1e6, 3), "unit": "Mpix/s",
+                   "cores": cores, "cpu_model": cpu_model(), "kind": "oracle",
+                   "sample": "FP64 C oracle (OpenMP over rows), %d pass(es) over the first %d frames "
+                             "of the same %s sequence, %.1f s" % (passes, n_cpu, wl.name, cpu_s)}
+            # the same oracle on one thread, over the first frame(s)
+            oracle.set_threads(1)
+            n1 = min(args.single_thread_frames, n_cpu)
+            o = make_oracle()
+            t1 = time.perf_counter()
+            for f in host_frames[:n1]:
+                step_oracle(o, f)
+            s1 = time.perf_counter() - t1
+            del o
+            oracle.set_threads(cores)
+            cpu["single_thread"] = {"value": round(n1 * npix / s1 / 1e6, 3), "unit": "Mpix/s",
+                                    "sample": "the first %d frame(s), %.1f s" % (n1, s1)}
+            res["cpu_baseline"] = cpu
+    del dev_frames, host_frames
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return res
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=60)
+    ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c2p", "c3", "c4", "c5", "ablation"],
-                    help="c2p: the c2 scene with the paper's own predictor and weight "
-                         "(Eq. 12-13, d = 4); ablation: PSNR of RLS vs weighted RLS, "
-                         "supplied vs temporal feature, with and without the blend")
-    ap.add_argument("--serve-seconds", type=float, default=15.0,
-                    help="c5 (and the default run's serving leg): wall seconds of serving")
+    ap.add_argument("--workload", default="c3",
+                    choices=["c1", "c2", "c2p", "c3", "c4", "c5", "ablation", "ablation_c3"],
+                    help="c3 (default): the 4K d = 10 FP16 headline plus the c2, c4 and "
+                         "serving legs; c2p: the c2 scene with the paper's own predictor and "
+                         "weight (Eq. 12-13, d = 4); ablation: PSNR of RLS vs weighted RLS, "
+                         "supplied vs temporal feature, fixed vs automatic lambda, with and "
+                         "without the blend (ablation_c3: on the c3 scene with its edits)")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="c3: skip the c2, c4 and serving legs")
+    ap.add_argument("--serve-seconds", type=float, default=12.0,
+                    help="wall seconds of serving the 32-session trace, per mode")
+    ap.add_argument("--saturating-seconds", type=float, default=8.0,
+                    help="wall seconds of serving the saturating trace, per mode")
     ap.add_argument("--budget-gb", type=float, default=0.0,
-                    help="c5: HBM budget for session state (0: 200 GB)")
-    ap.add_argument("--no-serving", action="store_true",
-                    help="default run: skip the short serving leg")
-    ap.add_argument("--pool", type=int, default=4,
-                    help="c4: distinct frames generated per stream (cycled)")
+                    help="serving: HBM budget for session state (0: 200 GB)")
+    ap.add_argument("--pool", type=int, default=0,
+                    help="distinct frames generated per stream (c4) or per resolution "
+                         "(serving), cycled (0: 4 in the default run, 60 with --workload c5)")
+    ap.add_argument("--tune", action="store_true", help="c4: autotune the batched launch shape")
+    ap.add_argument("--batch-tile", type=int, nargs=3, default=(8, 256, 0),
+                    metavar=("TILE_W_LOG2", "BLOCK_THREADS", "BLOCKS_PER_CU"),
+                    help="c4 launch shape without --tune (default: 256 x 1 tiles, one workgroup "
+                         "per tile, the autotuner's pick on the c4 mix)")
+    ap.add_argument("--serve-tile", type=int, nargs=3, default=(8, 256, 0),
+                    metavar=("TILE_W_LOG2", "BLOCK_THREADS", "BLOCKS_PER_CU"),
+                    help="serving launch shape (both modes)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--blend-sigmas", type=float, nargs=2, default=(1.5, 0.15),
                     metavar=("SIGMA_S", "SIGMA_R"),
                     help="widths of the timed 5x5 spatial blend (after the step loop)")
     ap.add_argument("--cpu-frames", type=int, default=0,
                     help="frames of the oracle sample (0: all frames of the sequence)")
+    ap.add_argument("--single-thread-frames", type=int, default=1,
+                    help="frames of the one-thread oracle sample")
+    ap.add_argument("--unrounded-frames", type=int, default=6,
+                    help="FP16 workloads: frames compared against the oracle fed the unrounded "
+                         "FP32 inputs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 10 plain device copies of MIB MiB (the known-size "
                          "reference for the HBM byte counters) and exit")
@@ -392,221 +705,71 @@ def main():
               % args.gpus, file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
-    import synth
     from paper_2106_08034_amd import build as hip_build
-    from paper_2106_08034_amd import wrls
 
     if hip_build.needs_build():
         hip_build.build()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
+    torch.cuda.set_device(torch.device("cuda:0"))
+    base = {"n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "data": DATA}
 
     if args.workload == "c4":
-        print(json.dumps(bench_batched(args)), flush=True)
+        args.pool = args.pool or 4
+        r = bench_batched(args, tune=args.tune)
+        line = dict(base, metric="denoised Mpix/s (wRLS step, batched) + % HBM roofline",
+                    value=r["batched"]["value"], unit="Mpix/s",
+                    ms_per_step=r["batched"]["ms_per_round"], dtype="f32 (f16 inputs)",
+                    config={"workload": r["workload"]}, roofline=dict(r["batched"]["roofline"],
+                                                                      traffic=None),
+                    c4=r, cpu_baseline=None)
+        print(json.dumps(line), flush=True)
         return
-    if args.workload == "ablation":
-        W, H, T, warm = 640, 360, 60, 10
+    if args.workload in ("ablation", "ablation_c3"):
+        c3 = args.workload == "ablation_c3"
+        W, H = 640, 360
+        T, warm = (30, 5) if c3 else (60, 10)
         t0 = time.perf_counter()
-        res = run_ablation(W, H, T, warm)
+        res = run_ablation(W, H, T, warm, scene="c3" if c3 else "c2")
         best = max(v.get("psnr_blend_db", 0.0) for k, v in res.items() if k != "input")
-        line = {"metric": "PSNR dB vs clean frames (ablation of Sec. 5.3)", "value": best,
-                "unit": "dB", "n_gpus": 1, "steps": T, "warmup": warm,
-                "ms_per_step": round((time.perf_counter() - t0) * 1e3 / T, 3),
-                "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-                "data": "synthetic (seeded procedural scene with its clean frames)",
-                "config": {"workload": "c2-scene-%dx%d-%dframes-ablation" % (W, H, T),
-                           "psnr_frames": "%d..%d" % (warm, T - 1), "blend_sigmas": [1.5, 0.15]},
-                "ablation": res, "cpu_baseline": None}
+        line = dict(base, metric="PSNR dB vs clean frames (ablation of Sec. 5.3)", value=best,
+                    unit="dB", steps=T, warmup=warm,
+                    ms_per_step=round((time.perf_counter() - t0) * 1e3 / T, 3), dtype="f32",
+                    data="synthetic (seeded procedural scene with its clean frames)",
+                    config={"workload": "%s-scene-%dx%d-%dframes-ablation" % ("c3" if c3 else "c2",
+                                                                              W, H, T),
+                            "psnr_frames": "%d..%d" % (warm, T - 1), "blend_sigmas": [1.5, 0.15]},
+                    ablation=res, cpu_baseline=None)
         print(json.dumps(line), flush=True)
         return
     if args.workload == "c5":
-        res = bench_serving(args)
-        line = {"metric": "denoised Mpix/s + p50/p99 frame latency @32 sessions (serving)",
-                "value": res["mpix_per_s"], "unit": "Mpix/s", "n_gpus": 1,
-                "steps": res["steps"], "warmup": 0,
-                "ms_per_step": round(res["seconds"] * 1e3 / max(1, res["steps"]), 4),
-                "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-                "dtype": "f32 (f16 inputs)",
-                "data": "synthetic (seeded sessions and procedural frames)",
-                "config": {"workload": "c5-32-sessions-poisson4-exp20s-720p..4k-30..60Hz-d8-f16",
-                           "serve_seconds": args.serve_seconds}, "serving": res,
-                "cpu_baseline": None}
+        args.pool = args.pool or 60
+        sv = bench_serving(args)
+        b = sv["c5"]["batched"]
+        line = dict(base, metric="denoised Mpix/s + p50/p99 frame latency @32 sessions (serving)",
+                    value=b["mpix_per_s"], unit="Mpix/s", steps=b["steps"], warmup=0,
+                    ms_per_step=round(b["seconds"] * 1e3 / max(1, b["steps"]), 4),
+                    dtype="f32 (f16 inputs)", data="synthetic (seeded sessions and procedural frames)",
+                    config={"workload": "c5-32-sessions-poisson4-exp20s-720p..4k-30..60Hz-d8-f16",
+                            "serve_seconds": args.serve_seconds}, serving=sv, cpu_baseline=None)
         print(json.dumps(line), flush=True)
         return
-    wl = make_workload(args.workload)
-    paper = args.workload == "c2p"
-    d_model = 4 if paper else wl.d
-    t0 = time.time()
-    src = synth.FrameSource(wl)
-    host_frames = []
-    dev_frames = []
-    for t in range(wl.frames):
-        f = src.next()
-        host_frames.append(f)
-        up = lambda a: torch.from_numpy(a).to(dev)
-        if paper:  # features and variance are not inputs of paper mode
-            dev_frames.append((up(f.color), None, None, up(f.motion)))
-        else:
-            dev_frames.append(tuple(up(a) for a in (f.color, f.feats, f.var, f.motion)))
-    torch.cuda.synchronize()
-    print("generated and uploaded %d frames of %s in %.1fs" % (wl.frames, wl.name, time.time() - t0),
-          file=sys.stderr, flush=True)
 
-    stream = wrls.Stream(wl.width, wl.height, d_model, lam=0.98, in_dtype=wl.in_dtype,
-                         weight_mode="paper" if paper else "invvar")
-    out = torch.empty((3, wl.height, wl.width), dtype=torch.float32, device=dev)
-    cs = torch.cuda.current_stream()
-
-    for i in range(args.warmup):
-        stream.step(*dev_frames[i % wl.frames], out=out)
-    torch.cuda.synchronize()
-
-    K = args.steps
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    ev[0].record(cs)
-    for i in range(K):
-        stream.step(*dev_frames[(args.warmup + i) % wl.frames], out=out)
-        ev[i + 1].record(cs)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    per_launch_ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(K)]
-    total_ev_ms = ev[0].elapsed_time(ev[K])
-
-    # The spatial blend (a second kernel after the step), timed on its own
-    # over the last state: K launches, HIP events on the launch stream.
-    f_last = dev_frames[(args.warmup + K - 1) % wl.frames][1]
-    fin = torch.empty_like(out)
-    ss, sr = args.blend_sigmas
-    stream.blend(f_last, out, ss, sr, out=fin)
-    torch.cuda.synchronize()
-    evb = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
-    evb[0].record(cs)
-    for i in range(K):
-        stream.blend(f_last, out, ss, sr, out=fin)
-        evb[i + 1].record(cs)
-    torch.cuda.synchronize()
-    blend_ms = [evb[i].elapsed_time(evb[i + 1]) for i in range(K)]
-    npix = wl.width * wl.height
-    mpix_s = K * npix / elapsed / 1e6
-    in_bytes = 2 if wl.in_dtype == "f16" else 4
-    if paper:
-        bpp = algorithmic_bytes_per_pixel_paper(in_bytes, motion=wl.motion != "static")
-    else:
-        bpp = algorithmic_bytes_per_pixel(wl.d, in_bytes, motion=wl.motion != "static")
-    avg_launch_s = float(np.mean(per_launch_ms)) / 1e3
-    achieved_gbs = bpp * npix / avg_launch_s / 1e9
-    traffic = load_traffic(args.workload)
-    copy_gbs = measure_copy_gbs(torch, wrls, bpp * npix)
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        # the oracle as it stands, on the same frames: whole passes over the
-        # first n_cpu frames of the sequence until about 10 s of CPU work
-        import oracle
-        n_cpu = args.cpu_frames or wl.frames
-
-        def make_oracle():
-            if paper:
-                return oracle.Oracle(wl.width, wl.height, 4, lam=0.98, wmode=oracle.W_PAPER)
-            return oracle.Oracle(wl.width, wl.height, wl.d, lam=0.98)
-
-        def step_oracle(o, f):
-            if paper:
-                o.step(f.color, None, None, f.motion)
-            else:
-                o.step(f.color, f.feats, f.var, f.motion)
-
-        passes = 0
-        frames_done = 0
-        tc = time.perf_counter()
-        while passes < 8 and (passes == 0 or time.perf_counter() - tc < 10.0):
-            o = make_oracle()
-            for f in host_frames[:n_cpu]:
-                step_oracle(o, f)
-            del o
-            passes += 1
-            frames_done += n_cpu
-        cpu_s = time.perf_counter() - tc
-        cores = oracle.threads()
-        cpu = {"value": round(frames_done * npix / cpu_s / 1e6, 3), "unit": "Mpix/s",
-               "cores": cores, "kind": "oracle",
-               "sample": "FP64 C oracle (OpenMP over rows), %d pass(es) over the first %d frames "
-                         "of the same %s sequence, %.1f s" % (passes, n_cpu, wl.name, cpu_s)}
-        # the same oracle on one thread, over the first 3 frames
-        oracle.set_threads(1)
-        n1 = min(3, n_cpu)
-        t1 = time.perf_counter()
-        o = make_oracle()
-        for f in host_frames[:n1]:
-            step_oracle(o, f)
-        del o
-        s1 = time.perf_counter() - t1
-        oracle.set_threads(cores)
-        cpu["single_thread"] = {"value": round(n1 * npix / s1 / 1e6, 3), "unit": "Mpix/s",
-                                "sample": "the first %d frames, %.1f s" % (n1, s1)}
-
-    line = {
-        "metric": "denoised Mpix/s (wRLS step) + % HBM roofline",
-        "value": round(mpix_s, 2),
-        "unit": "Mpix/s",
-        "n_gpus": 1,
-        "steps": K,
-        "warmup": args.warmup,
-        "ms_per_step": round(elapsed * 1e3 / K, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32" if wl.in_dtype == "f32" else "f32 (f16 inputs)",
-        "data": "synthetic (seeded procedural scene, lognormal per-pixel noise variance)",
-        "config": {"workload": wl.name + ("-paper-mode-d4" if paper else ""),
-                   "width": wl.width, "height": wl.height, "d": d_model,
-                   "frames_in_sequence": wl.frames, "lambda": 0.98,
-                   "input_dtype": wl.in_dtype, "state_dtype": "f32"},
-        "roofline": {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
-                     "traffic": traffic,
-                     "kernel": "wrls paper_step_kernel" if paper else "wrls step_kernel<%d>" % wl.d,
-                     "algorithmic_bytes_per_pixel": bpp,
-                     "avg_launch_us": round(avg_launch_s * 1e6, 2),
-                     "launch_us_min_max": [round(min(per_launch_ms) * 1e3, 2),
-                                           round(max(per_launch_ms) * 1e3, 2)],
-                     "event_total_ms": round(total_ev_ms, 3),
-                     "measured_copy": {"kernel": "wrls_device_copy, same bytes per launch",
-                                       "gbs": round(copy_gbs, 1),
-                                       "frac": round(achieved_gbs / copy_gbs, 4)}},
-        "cpu_baseline": cpu,
-    }
-    bbpp = blend_bytes_per_pixel(d_model, in_bytes, paper)
-    blend_s = float(np.mean(blend_ms)) / 1e3
-    line["spatial_blend"] = {
-        "kernel": "wrls blend_kernel<%d>" % d_model, "sigma_s": ss, "sigma_r": sr,
-        "avg_launch_us": round(blend_s * 1e6, 2), "mpix_per_s": round(npix / blend_s / 1e6, 1),
-        "algorithmic_bytes_per_pixel": bbpp,
-        "achieved": round(bbpp * npix / blend_s / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(bbpp * npix / blend_s / 1e9 / HBM_PEAK_GBS, 4),
-        "traffic": load_traffic(args.workload, "blend"),
-        "step_plus_blend_mpix_per_s": round(npix / (avg_launch_s + blend_s) / 1e6, 1)}
-    # the blend is bound by vector ALU work, not HBM: its arithmetic rate too
-    bflop = blend_flop_per_pixel(d_model)
-    alu_tflops = bflop * npix / blend_s / 1e12
-    line["spatial_blend"]["alu"] = {
-        "bound": "alu", "flop_per_pixel": bflop, "achieved": round(alu_tflops, 2),
-        "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-        "frac": round(alu_tflops / FP32_VECTOR_PEAK_TFLOPS, 4)}
-    stream.close()
-    if not args.no_serving and args.workload == "c2":
-        del dev_frames
+    r = bench_step(args, args.workload, with_cpu=not args.no_cpu_baseline)
+    line = dict(base, metric=METRIC if args.workload == "c3" else
+                "denoised Mpix/s (wRLS step) + % HBM roofline", **r)
+    line.setdefault("cpu_baseline", None)
+    if args.workload == "c3" and not args.headline_only:
+        # the other configurations, each in its own key
+        c2 = bench_step(args, "c2", with_cpu=False, parity_frames=10, with_blend=True)
+        line["c2"] = {k: c2[k] for k in ("value", "unit", "ms_per_step", "config", "roofline",
+                                         "parity", "spatial_blend")}
+        args.pool = args.pool or 4
+        line["c4_batched"] = bench_batched(args, tune=args.tune)
         torch.cuda.empty_cache()
-        sv = bench_serving(args)
-        line["serving_32_sessions"] = {k: sv[k] for k in ("mpix_per_s", "p50_ms", "p99_ms", "max_ms",
-                                                          "frames", "steps", "max_concurrent",
-                                                          "sessions_served", "seconds")}
+        line["serving"] = bench_serving(args)
     print(json.dumps(line), flush=True)
 
 

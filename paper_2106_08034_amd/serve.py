@@ -13,6 +13,10 @@ cross-stream waits and lets the two in-flight steps overlap on the device.
 Latency is measured on the host from a frame's arrival to the moment its
 step is seen complete.
 
+The per-stream baseline serves the same trace with one wrls_step launch per
+ready frame (no batching), alternating between the same two HIP streams,
+with up to two launches per batch slot in flight.
+
 The scheduling rules (arena, admission, batch composition) are plain
 Python, independent of the GPU; Server drives them against the library.
 """
@@ -24,6 +28,12 @@ import time
 from typing import Dict, List, Optional, Sequence, Tuple
 
 ALIGN = 256
+
+# The saturating variant of the 32-session serving trace: arrivals at 16/s
+# instead of 4/s and frame rates of 120-240 Hz instead of 30-60, which offers
+# 11-17 Gpx/s from t = 3 s on, more than one GPU steps at d = 8 with FP16
+# inputs (keyword arguments of synth.c5_sessions).
+SATURATING = dict(rate=16.0, fps_range=(120.0, 240.0))
 
 
 class Arena:
@@ -134,6 +144,19 @@ class Scheduler:
         ready.sort(key=lambda s: s.frame_time(s.next_frame))
         return ready[: self.max_batch]
 
+    def next_launches(self, now: float, per_stream: bool, slots: int) -> List[List[SessionState]]:
+        """The launches to issue now, given `slots` free launch slots:
+        batched, one launch of next_batch(now); per stream, one launch per
+        session of next_batch(now), at most `slots` of them."""
+        if slots <= 0:
+            return []
+        members = self.next_batch(now)
+        if not members:
+            return []
+        if per_stream:
+            return [[s] for s in members[:slots]]
+        return [members]
+
     def retire(self, now: float) -> List[SessionState]:
         """Ends sessions past their end with nothing in flight; frees memory."""
         gone = [s for s in self.active
@@ -160,12 +183,18 @@ class Server:
     """Runs a session workload in real time on the GPU."""
 
     def __init__(self, budget_bytes: int, d: int = 8, in_dtype: str = "f16", max_batch: int = 32,
-                 lam: float = 0.98, tile: Optional[Tuple[int, int, int]] = None):
+                 lam: float = 0.98, tile: Optional[Tuple[int, int, int]] = None,
+                 per_stream: bool = False):
+        """per_stream: serve with one wrls_step launch per frame (the
+        unbatched baseline) instead of batched steps."""
         import torch
 
         from . import wrls
         self.torch, self.wrls = torch, wrls
         self.d, self.in_dtype, self.lam = d, in_dtype, lam
+        self.per_stream = per_stream
+        # launches in flight: two batched steps, or two per batch slot
+        self.max_inflight = 2 * max_batch if per_stream else 2
         self.arena_mem = torch.empty(budget_bytes + ALIGN, dtype=torch.uint8, device="cuda")
         self.delta = (-self.arena_mem.data_ptr()) % ALIGN   # first aligned byte
         self.batches = [wrls.Batch(max_batch, d, in_dtype) for _ in range(2)]
@@ -177,6 +206,10 @@ class Server:
         # stream (their work is complete by then, so the close need not wait)
         self.idle = torch.cuda.Stream()
         self.sched = Scheduler(budget_bytes, self.footprint, max_batch)
+        if per_stream and tile is not None:
+            self.stream_tile = tile
+        else:
+            self.stream_tile = None
         self.streams: Dict[int, object] = {}
         self.outs: Dict[int, object] = {}
         self.created: Dict[int, object] = {}   # sid -> event after its initialisation
@@ -197,6 +230,8 @@ class Server:
                                           in_dtype=self.in_dtype,
                                           hip_stream=self.batches[0].hip_stream,
                                           device_mem=(ptr, nstate))
+        if self.stream_tile is not None:
+            self.streams[s.sid].set_tile(self.stream_tile[0], self.stream_tile[1], 0)
         ev = torch.cuda.Event()
         ev.record(self.hip[0])
         self.created[s.sid] = ev
@@ -257,28 +292,34 @@ class Server:
             if now >= seconds or (not pending and not self.sched.active and not self.sched.waiting
                                   and not inflight):
                 break
-            if len(inflight) < 2:
-                members = self.sched.next_batch(now)
-                if members:
-                    bi = steps % 2
-                    for s in members:   # a new session's initialisation ran on hip[0]
-                        ev = self.created.pop(s.sid, None)
-                        if ev is not None and bi != 0:
-                            self.hip[bi].wait_event(ev)
-                    frames = []
-                    for s in members:
-                        pool = frame_pools[(s.width, s.height)]
-                        frames.append(pool[s.next_frame % len(pool)])
+            launches = self.sched.next_launches(now, self.per_stream,
+                                                self.max_inflight - len(inflight))
+            for members in launches:
+                bi = steps % 2
+                for s in members:   # a new session's initialisation ran on hip[0]
+                    ev = self.created.pop(s.sid, None)
+                    if ev is not None and bi != 0:
+                        self.hip[bi].wait_event(ev)
+                frames = []
+                for s in members:
+                    pool = frame_pools[(s.width, s.height)]
+                    frames.append(pool[s.next_frame % len(pool)])
+                if self.per_stream:
+                    st = self.streams[members[0].sid]
+                    self.wrls.wrls_set_hip_stream(st.handle, self.hip[bi].cuda_stream)
+                    st.step(*frames[0], out=self.outs[members[0].sid])
+                else:
                     self.batches[bi].step([self.streams[s.sid] for s in members], frames,
                                           [self.outs[s.sid] for s in members])
-                    ev = torch.cuda.Event()
-                    ev.record(self.hip[bi])
-                    for s in members:
-                        s.in_flight = True
-                        s.next_frame += 1
-                    inflight.append((ev, members, sum(s.width * s.height for s in members)))
-                    steps += 1
-                    continue
+                ev = torch.cuda.Event()
+                ev.record(self.hip[bi])
+                for s in members:
+                    s.in_flight = True
+                    s.next_frame += 1
+                inflight.append((ev, members, sum(s.width * s.height for s in members)))
+                steps += 1
+            if launches:
+                continue
             time.sleep(poll)
         for entry in inflight:
             entry[0].synchronize()
@@ -291,6 +332,7 @@ class Server:
         lat = [x for s in self.sched.done for x in s.latencies]
         waits = [s.admitted_at - s.arrival for s in self.sched.done if s.admitted_at is not None]
         return {
+            "mode": "per_stream_launches" if self.per_stream else "batched",
             "seconds": round(wall, 3),
             "steps": steps,
             "frames": len(lat),

@@ -3,7 +3,7 @@ batch composition, retirement."""
 import pytest
 
 import synth
-from paper_2106_08034_amd.serve import ALIGN, Arena, Scheduler, SessionState, percentile
+from paper_2106_08034_amd.serve import ALIGN, SATURATING, Arena, Scheduler, SessionState, percentile
 
 
 def test_arena_first_fit_alignment_and_coalescing():
@@ -82,3 +82,37 @@ def test_percentile():
     assert percentile([3, 1, 2], 50) == 2
     assert percentile([1, 2, 3, 4], 100) == 4
     assert percentile(list(range(101)), 99) == pytest.approx(99)
+
+
+def test_launches_batched_against_per_stream():
+    """The per-stream baseline issues one launch per due frame, the same
+    frames in the same order as the batched step, within its free launch
+    slots; the batched mode issues one launch, or none without a free slot."""
+    sch = Scheduler(budget=10 ** 9, footprint=lambda w, h: 1000, max_batch=3)
+    ss = [_sess(i, fps=100) for i in range(4)]
+    for s in ss:
+        sch.arrive(s)
+    sch.admit(0.0)
+    ss[1].next_frame = 1           # due at 0.01 s: after the others
+    batched = sch.next_launches(0.02, per_stream=False, slots=1)
+    assert [[s.sid for s in m] for m in batched] == [[0, 2, 3]]
+    assert sch.next_launches(0.02, per_stream=False, slots=0) == []
+    single = sch.next_launches(0.02, per_stream=True, slots=8)
+    assert [[s.sid for s in m] for m in single] == [[0], [2], [3]]
+    assert [[s.sid for s in m] for m in sch.next_launches(0.02, True, 2)] == [[0], [2]]
+    for s in ss:
+        s.in_flight = True
+    assert sch.next_launches(0.02, True, 8) == [] and sch.next_launches(0.02, False, 2) == []
+
+
+def test_saturating_trace_offers_more_than_the_step_rate():
+    """The saturating variant of the serving trace (arrivals at 16/s, frame
+    rates 120-240 Hz) offers more pixels per second from t = 3 s on than one
+    GPU steps at d = 8 FP16 (about 10 Gpx/s measured); the plain trace offers
+    at most about 4 Gpx/s."""
+    def offered(sessions, t):
+        return sum(s.width * s.height * s.fps for s in sessions if s.arrival <= t < s.arrival + s.duration)
+    plain = synth.c5_sessions()
+    sat = synth.c5_sessions(**SATURATING)
+    assert min(offered(sat, t) for t in (3, 5, 8, 10)) > 11e9
+    assert max(offered(plain, t) for t in range(16)) < 4.5e9
