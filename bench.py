@@ -21,6 +21,7 @@ Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import gc
 import hashlib
 import json
 import os
@@ -278,8 +279,11 @@ def bench_serving(args, modes=("batched", "per_stream"), saturating=True):
             out[name][mode] = res
             print("serving %s %s: %.0f Mpix/s, p50 %.3f ms, p99 %.3f ms" % (
                 name, mode, res["mpix_per_s"], res["p50_ms"], res["p99_ms"]), file=sys.stderr, flush=True)
-            del srv
             torch.cuda.synchronize()
+            srv.close()
+            del srv
+            gc.collect()
+            torch.cuda.empty_cache()
     if "batched" in modes and "per_stream" in modes:
         for name in out:
             b, s = out[name]["batched"], out[name]["per_stream"]

@@ -300,6 +300,34 @@ wrls_status wrls_batch_use_graph(wrls_batch *b, int32_t enable);
 wrls_status wrls_batch_step(wrls_batch *b, int32_t n, wrls_stream *const *streams,
                             const wrls_frame *frames);
 
+/* ---- A batched step that allocates nothing --------------------------------
+ *
+ * For callers that cannot allocate device memory when they step: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * wrls_batch_step keeps its frame table in device memory that
+ * wrls_batch_create allocates; this variant needs no wrls_batch: the table
+ * lives in a fixed array of the library, one per device (about 9 KB, held
+ * until the process ends), written by small kernels whose arguments carry
+ * it (no copy, no memset, no pinned staging), followed by the same batched
+ * kernel with one workgroup per tile.  The call allocates nothing, on the
+ * device or the host.  Streams created with wrls_create_stream_in allocate
+ * nothing either.
+ *
+ * One frame for each of streams[0..n-1] (distinct handles with the same d
+ * and input type, not WRLS_W_PAPER; 0 <= n <= WRLS_NOALLOC_MAX_STREAMS);
+ * frames[i] belongs to streams[i].  tile_w_log2 and block_threads give the
+ * tile as in wrls_set_tile.  Enqueued on hip_stream (a hipStream_t; NULL:
+ * the null stream), which must be ordered with the streams' other work;
+ * returns without synchronising.  Each stream's result is bitwise the same
+ * as with wrls_step or wrls_batch_step.  Every call on a device shares that
+ * device's table and it keeps the last call's contents: two calls whose
+ * work overlaps on one device (on different HIP streams, or from several
+ * host threads) race and must not be issued.  WRLS_EINVAL for n above the
+ * maximum or a bad argument; nothing is enqueued then. */
+#define WRLS_NOALLOC_MAX_STREAMS 64
+wrls_status wrls_batch_step_noalloc(int32_t n, wrls_stream *const *streams, const wrls_frame *frames,
+                                    int32_t tile_w_log2, int32_t block_threads, void *hip_stream);
+
 /* Device-to-device copy of `bytes` bytes, in the state kernels' access
  * form: 16-byte loads and non-temporal 16-byte stores, one vector per
  * thread.  A utility (for example to snapshot outputs), and the read+write

@@ -712,6 +712,68 @@ wrls_status wrls_batch_step(wrls_batch *b, int32_t n, wrls_stream *const *stream
     return WRLS_OK;
 }
 
+wrls_status wrls_batch_step_noalloc(int32_t n, wrls_stream *const *streams, const wrls_frame *frames,
+                                    int32_t tile_w_log2, int32_t block_threads, void *hip_stream)
+{
+    if (n < 0 || n > WRLS_NOALLOC_MAX_STREAMS)
+        return fail(WRLS_EINVAL, "n = %d outside [0, %d]: the fixed frame table holds %d frames", n,
+                    WRLS_NOALLOC_MAX_STREAMS, WRLS_NOALLOC_MAX_STREAMS);
+    if (n == 0) return WRLS_OK;
+    if (!streams || !frames) return fail(WRLS_EINVAL, "streams or frames is NULL");
+    if (block_threads != 64 && block_threads != 128 && block_threads != 256)
+        return fail(WRLS_EINVAL, "block_threads = %d not in {64, 128, 256}", block_threads);
+    if (tile_w_log2 < 0 || (1 << tile_w_log2) > block_threads)
+        return fail(WRLS_EINVAL, "tile width 2^%d exceeds %d threads", tile_w_log2, block_threads);
+    for (int i = 0; i < n; i++) {
+        const wrls_stream *s = streams[i];
+        if (!s) return fail(WRLS_EINVAL, "streams[%d] is NULL", i);
+        if (s->prm.weight_mode == WRLS_W_PAPER)
+            return fail(WRLS_EUNSUPPORTED, "streams[%d]: batches do not take WRLS_W_PAPER streams", i);
+        if (s->prm.d != streams[0]->prm.d || s->prm.in_dtype != streams[0]->prm.in_dtype)
+            return fail(WRLS_EINVAL, "streams[%d] has d = %d, dtype %d; streams[0] has d = %d, dtype %d",
+                        i, s->prm.d, s->prm.in_dtype, streams[0]->prm.d, streams[0]->prm.in_dtype);
+        for (int k = 0; k < i; k++)
+            if (streams[k] == s) return fail(WRLS_EINVAL, "stream appears twice (%d and %d)", k, i);
+    }
+    // the table is built on the host (no allocation: a local) and written to
+    // the device's fixed table by kernels whose arguments carry it
+    wrls::BatchTable t;
+    t.n = n;
+    t.tile = wrls::TileShape{tile_w_log2, block_threads, 0};
+    t.prefix[0] = 0;
+    const int tw = 1 << tile_w_log2;
+    const int th = block_threads >> tile_w_log2;
+    for (int k = 0; k < n; k++) {
+        const wrls_frame &f = frames[k];
+        wrls_status rc = frame_args(streams[k], f.color, f.features, f.variance, f.motion, f.out,
+                                    &t.frame[k]);
+        if (rc != WRLS_OK) {
+            char msg[sizeof g_err];
+            std::snprintf(msg, sizeof msg, "%s", g_err);
+            return fail(rc, "frames[%d]: %s", k, msg);
+        }
+        wrls::FrameArgs &a = t.frame[k];
+        a.tiles_x = (a.W + tw - 1) / tw;
+        a.tiles_y = (a.H + th - 1) / th;
+        a.strip_w = a.tiles_x;
+        t.prefix[k + 1] = t.prefix[k] + a.tiles_x * a.tiles_y;
+    }
+    t.total_tiles = t.prefix[n];
+    wrls::BatchTable *dev_tab = nullptr;
+    hipError_t e = wrls::noalloc_table(&dev_tab);
+    if (e != hipSuccess) return hip_fail(e, "address of the fixed frame table");
+    const hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    e = wrls::launch_fill_table(dev_tab, t, st);
+    if (e != hipSuccess) return hip_fail(e, "frame table launch");
+    // one workgroup per tile, a multiple of 8 (one part per XCD)
+    const int32_t grid = t.total_tiles < 8 ? 8 : (t.total_tiles + 7) / 8 * 8;
+    e = wrls::launch_step_batched(streams[0]->prm.d, streams[0]->prm.in_dtype == WRLS_F16, dev_tab,
+                                  grid, block_threads, st);
+    if (e != hipSuccess) return hip_fail(e, "batched step launch");
+    for (int k = 0; k < n; k++) advance(streams[k]);
+    return WRLS_OK;
+}
+
 wrls_status wrls_get_history(const wrls_stream *s, float *z)
 {
     if (!s) return fail(WRLS_EINVAL, "stream handle is NULL");

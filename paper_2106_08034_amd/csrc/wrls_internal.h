@@ -167,6 +167,11 @@ hipError_t launch_blend(int d, bool f16, bool paper, const BlendArgs &a, hipStre
 // threads over every tile of every frame in the device table `tab`.
 hipError_t launch_step_batched(int d, bool f16, const BatchTable *tab, int32_t grid,
                                int32_t block_threads, hipStream_t st);
+// Steps that allocate nothing: the device address of this device's fixed
+// frame table (looked up once per device), and the launches that write a
+// host-built table into it (kernel arguments carry the table; no copy).
+hipError_t noalloc_table(BatchTable **tab);
+hipError_t launch_fill_table(BatchTable *tab, const BatchTable &host, hipStream_t st);
 // The batched kernel's entry point (for graph kernel nodes); null for a bad d.
 const void *batched_kernel_fn(int d, bool f16);
 // Workgroups of block_threads threads of the batched kernel that fit on one

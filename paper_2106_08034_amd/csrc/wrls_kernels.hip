@@ -16,6 +16,8 @@
 // most two such runs per tap row, which the L1/L2 caches merge.  Tiles are
 // handed to the eight XCDs in contiguous ranges so neighbouring tiles, which
 // share source rows, meet in one L2.
+#include <mutex>
+
 #include "wrls_internal.h"
 
 namespace wrls {
@@ -1009,6 +1011,35 @@ blend_kernel(const BlendArgs a)
             for (int c = 0; c < 3; c++) bstore(r_out, jr[r] * 4u, (uint32_t)c * n * 4u, outc[r][c]);
 }
 
+// A part of a batched step's frame table, passed by value as a kernel
+// argument (1.2 KB): frames k0 .. k0 + m - 1 and their prefix entries
+// k0 .. k0 + m; the part with k0 = 0 also carries the header.
+constexpr int kChunkFrames = 8;
+struct TableChunk {
+    int32_t k0, m;
+    int32_t n, total_tiles;
+    TileShape tile;
+    int32_t prefix[kChunkFrames + 1];
+    FrameArgs frame[kChunkFrames];
+};
+static_assert(sizeof(FrameArgs) % 4 == 0, "frames are copied as 32-bit words");
+
+// Writes one part of a frame table into device memory (one workgroup,
+// 32-bit words, plain global stores).
+__global__ void __launch_bounds__(256) fill_table_kernel(BatchTable *tab, const TableChunk c)
+{
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(c.frame);
+    uint32_t *dst = reinterpret_cast<uint32_t *>(tab->frame + c.k0);
+    const int words = c.m * (int)(sizeof(FrameArgs) / 4);
+    for (int i = (int)threadIdx.x; i < words; i += (int)blockDim.x) dst[i] = src[i];
+    if ((int)threadIdx.x <= c.m) tab->prefix[c.k0 + (int)threadIdx.x] = c.prefix[threadIdx.x];
+    if (c.k0 == 0 && threadIdx.x == 0) {
+        tab->n = c.n;
+        tab->total_tiles = c.total_tiles;
+        tab->tile = c.tile;
+    }
+}
+
 template <int D>
 hipError_t launch_blend_d(bool f16, bool paper, const BlendArgs &a, hipStream_t st)
 {
@@ -1042,6 +1073,57 @@ hipError_t launch_batched_d(bool f16, const BatchTable *tab, int32_t grid, int32
 }
 
 }  // namespace
+
+// The frame table of steps that allocate nothing (wrls_batch_step_noalloc):
+// one table per device in a fixed device array, held until the process
+// ends (sizeof(BatchTable), about 9 KB).  Host code must not use the array's
+// name as an address: it reaches the array through the address that
+// hipGetSymbolAddress returns, looked up once per device with that device
+// current.  Every such step on a device shares the one table, so steps that
+// overlap on a device race.
+static __device__ __align__(256) unsigned char scratch[sizeof(BatchTable)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+BatchTable *g_scratch_ptr[kMaxDevices];
+}  // namespace
+
+hipError_t noalloc_table(BatchTable **tab)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = static_cast<BatchTable *>(ptr);
+    }
+    *tab = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+hipError_t launch_fill_table(BatchTable *tab, const BatchTable &host, hipStream_t st)
+{
+    (void)hipGetLastError();  // report this launch's error, not an older one
+    for (int k0 = 0; k0 == 0 || k0 < host.n; k0 += kChunkFrames) {
+        TableChunk c{};
+        c.k0 = k0;
+        c.m = host.n - k0 < kChunkFrames ? host.n - k0 : kChunkFrames;
+        c.n = host.n;
+        c.total_tiles = host.total_tiles;
+        c.tile = host.tile;
+        for (int i = 0; i <= c.m; i++) c.prefix[i] = host.prefix[k0 + i];
+        for (int i = 0; i < c.m; i++) c.frame[i] = host.frame[k0 + i];
+        hipLaunchKernelGGL(fill_table_kernel, dim3(1), dim3(256), 0, st, tab, c);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
 
 hipError_t launch_reset(float *state, int64_t npix, int d, int S, float p0, hipStream_t st)
 {

@@ -214,6 +214,21 @@ class Server:
         self.outs: Dict[int, object] = {}
         self.created: Dict[int, object] = {}   # sid -> event after its initialisation
 
+    def close(self):
+        """Releases the arena and the batch contexts (a Server's scheduler
+        refers back to it, so it is not freed by reference counting alone)."""
+        for sid in list(self.streams):
+            h = self.streams.pop(sid)
+            self.wrls.wrls_set_hip_stream(h.handle, self.idle.cuda_stream)
+            h.close()
+        self.outs.clear()
+        self.created.clear()
+        for b in self.batches:
+            b.close()
+        self.batches = []
+        self.arena_mem = None
+        self.sched = None
+
     def footprint(self, width: int, height: int) -> int:
         """Device bytes a session holds: both state copies and its output."""
         p = self.wrls.make_params(width, height, self.d, lam=self.lam, in_dtype=self.in_dtype)

@@ -46,6 +46,7 @@ class wrls_frame(ctypes.Structure):
 
 
 WRLS_MAX_BATCH = 64
+WRLS_NOALLOC_MAX_STREAMS = 64
 
 # Every symbol include/wrls.h declares, with its ctypes signature.
 _P = ctypes.POINTER(wrls_params)
@@ -79,6 +80,9 @@ SIGNATURES = {
     "wrls_batch_use_graph": (ctypes.c_int, [_VP, ctypes.c_int32]),
     "wrls_batch_step": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.POINTER(_VP),
                                        ctypes.POINTER(wrls_frame)]),
+    "wrls_batch_step_noalloc": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(_VP),
+                                               ctypes.POINTER(wrls_frame), ctypes.c_int32,
+                                               ctypes.c_int32, _VP]),
     "wrls_device_copy": (ctypes.c_int, [_VP, _VP, ctypes.c_size_t, _VP]),
     "wrls_last_error": (ctypes.c_char_p, []),
     "wrls_version": (ctypes.c_char_p, []),
@@ -229,6 +233,18 @@ def wrls_batch_step(b: int, handles, frames):
     hs = (ctypes.c_void_p * max(n, 1))(*handles)
     fs = (wrls_frame * max(n, 1))(*[wrls_frame(*[_ptr(t) for t in f]) for f in frames])
     _check(lib().wrls_batch_step(b, n, hs, fs))
+
+
+def wrls_batch_step_noalloc(handles, frames, tile_w_log2: int = 7, block_threads: int = 128,
+                            hip_stream: Optional[int] = None):
+    """One batched step that allocates nothing (the frame table is the
+    library's fixed per-device array); handles and frames as in
+    wrls_batch_step; hip_stream None: torch's current stream."""
+    n = len(handles)
+    hs = (ctypes.c_void_p * max(n, 1))(*handles)
+    fs = (wrls_frame * max(n, 1))(*[wrls_frame(*[_ptr(t) for t in f]) for f in frames])
+    st = _current_hip_stream() if hip_stream is None else hip_stream
+    _check(lib().wrls_batch_step_noalloc(n, hs, fs, tile_w_log2, block_threads, st))
 
 
 def wrls_blend(h: int, features, temporal, sigma_s: float, sigma_r: float, out):

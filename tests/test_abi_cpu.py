@@ -202,3 +202,21 @@ def test_device_copy_rejects_bad_arguments_on_the_host():
     assert L.wrls_device_copy(4096, 4096 + 32, 64, None) == wrls.WRLS_EINVAL  # overlap
     assert L.wrls_device_copy(4096 + 32, 4096, 64, None) == wrls.WRLS_EINVAL
     assert "overlap" in wrls.wrls_last_error()
+
+
+def test_noalloc_step_rejects_beyond_its_table_on_the_host():
+    """The allocation-free batched step holds at most WRLS_NOALLOC_MAX_STREAMS
+    frames in its fixed table: more (or a negative count, or a bad tile) is
+    refused before anything reaches the GPU; n = 0 is a no-op."""
+    L = wrls.lib()
+    assert wrls.WRLS_NOALLOC_MAX_STREAMS == 64
+    assert L.wrls_batch_step_noalloc(65, None, None, 7, 128, None) == wrls.WRLS_EINVAL
+    assert "65" in wrls.wrls_last_error() and "64" in wrls.wrls_last_error()
+    assert L.wrls_batch_step_noalloc(-1, None, None, 7, 128, None) == wrls.WRLS_EINVAL
+    assert L.wrls_batch_step_noalloc(0, None, None, 7, 128, None) == wrls.WRLS_OK
+    assert L.wrls_batch_step_noalloc(1, None, None, 7, 128, None) == wrls.WRLS_EINVAL
+    hs = (ctypes.c_void_p * 1)(None)
+    fs = (wrls.wrls_frame * 1)()
+    assert L.wrls_batch_step_noalloc(1, hs, fs, 8, 128, None) == wrls.WRLS_EINVAL   # tile too wide
+    assert L.wrls_batch_step_noalloc(1, hs, fs, 7, 96, None) == wrls.WRLS_EINVAL
+    assert L.wrls_batch_step_noalloc(1, hs, fs, 7, 128, None) == wrls.WRLS_EINVAL   # NULL stream

@@ -1,0 +1,79 @@
+"""The batched step that allocates nothing (wrls_batch_step_noalloc, frame
+table in the library's fixed per-device array) against the batched step
+with an allocated table (wrls_batch_step): bitwise the same outputs and
+state, on two calls in a row, the second with fewer and smaller streams;
+and a stream stepped this way matches the FP64 oracle."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import synth
+from parity import G1_TOL, g1, log, predictor, term_scale, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    yield
+
+
+def _frames(wls, t):
+    out = []
+    for wl in wls:
+        src = synth.FrameSource(wl)
+        fs = [src.next() for _ in range(t)]
+        out.append(fs)
+    return out
+
+
+def test_noalloc_equals_allocated_table_twice_second_smaller():
+    import oracle
+    import torch
+    from paper_2106_08034_amd import wrls
+    wls = synth.c4_streams(frames=2, scale=0.1)[:6]
+    host = _frames(wls, 2)
+    dev = [[tuple(to_dev(x) for x in (f.color, f.feats, f.var, f.motion)) for f in fs] for fs in host]
+    cs = torch.cuda.current_stream().cuda_stream
+    b = wrls.Batch(len(wls), 8, "f16", hip_stream=cs)
+    ref = [wrls.Stream(wl.width, wl.height, 8, in_dtype="f16", hip_stream=cs) for wl in wls]
+    # the allocation-free path's streams live in caller memory too
+    mem = []
+    nal = []
+    for wl in wls:
+        p = wrls.make_params(wl.width, wl.height, 8, in_dtype="f16")
+        need = wrls.wrls_stream_device_bytes(p)
+        buf = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
+        ptr = (buf.data_ptr() + 255) // 256 * 256
+        mem.append(buf)
+        nal.append(wrls.Stream(wl.width, wl.height, 8, in_dtype="f16", hip_stream=cs,
+                               device_mem=(ptr, need)))
+    o = oracle.Oracle(wls[0].width, wls[0].height, 8)
+    # call 1: all six streams; call 2: the first two, which are also the
+    # smaller input (fewer frames, fewer tiles)
+    for call, members in enumerate((list(range(6)), [0, 1])):
+        t = call
+        log("case noalloc call %d: %s" % (call, [(wls[i].width, wls[i].height) for i in members]))
+        outs_ref = b.step([ref[i] for i in members], [dev[i][t] for i in members])
+        outs = [torch.full((3, wls[i].height, wls[i].width), float("nan"), device="cuda") for i in members]
+        frames = [dev[i][t] + (outs[k],) for k, i in enumerate(members)]
+        wrls.wrls_batch_step_noalloc([nal[i].handle for i in members], frames, 7, 128)
+        torch.cuda.synchronize()
+        for k, i in enumerate(members):
+            assert torch.equal(outs[k], outs_ref[k]), (call, i)
+            P0, B0 = ref[i].get_state()
+            P1, B1 = nal[i].get_state()
+            assert torch.equal(P0, P1) and torch.equal(B0, B1), (call, i)
+        f = host[0][t]
+        r = o.step(f.color, f.feats, f.var, f.motion)
+        e = g1(outs[0].cpu().numpy(), r, term_scale(o.get_beta(), predictor(f.feats)))
+        assert e <= G1_TOL, (call, e)
+    assert all(s.frames == 2 for s in (nal[0], nal[1])) and nal[5].frames == 1
+    for s in nal:
+        s.close()
+    b.close()
+    torch.cuda.synchronize()
