@@ -234,16 +234,36 @@ def run_ablation(width: int, height: int, frames: int, warm: int, sigma_s: float
     return res
 
 
-def _frame_pools(torch, shapes, count):
-    """Device frames of the serving recipe, `count` per (width, height)."""
+def _frame_pools(torch, shapes, count, host=None):
+    """Device frames of the serving recipe, `count` per (width, height);
+    host, if given, receives the host frames of the smallest resolution."""
     import synth
     pools = {}
+    smallest = min(shapes, key=lambda s: s[0] * s[1])
     for i, (w, h) in enumerate(shapes):
         src = synth.FrameSource(synth.c5_frame_pool(w, h, count), stream=i)
+        frames = [src.next() for _ in range(count)]
+        if host is not None and (w, h) == smallest:
+            host[(w, h)] = frames
         pools[(w, h)] = [tuple(torch.from_numpy(a).cuda() for a in (f.color, f.feats, f.var, f.motion))
-                         for f in (src.next() for _ in range(count))]
+                         for f in frames]
     torch.cuda.synchronize()
     return pools
+
+
+def serving_parity(torch, session, recorded, host_frames):
+    """G1 of a served session's outputs (host copies, in frame order) against
+    the FP64 oracle fed the same cycled frames."""
+    import oracle
+    o = oracle.Oracle(session.width, session.height, 8, lam=0.98)
+    par = _Parity(torch)
+    for k, out in enumerate(recorded):
+        f = host_frames[k % len(host_frames)]
+        ref, scale = o.step(f.color, f.feats, f.var, f.motion, want_scale=True)
+        par.add(out.cuda(), ref, scale)
+    r = par.report()
+    r["session"] = "%dx%d (sid %d), served batched" % (session.width, session.height, session.sid)
+    return r
 
 
 def bench_serving(args, modes=("batched", "per_stream"), saturating=True):
@@ -260,7 +280,8 @@ def bench_serving(args, modes=("batched", "per_stream"), saturating=True):
     from paper_2106_08034_amd.serve import SATURATING, Server
 
     t0 = time.time()
-    pools = _frame_pools(torch, synth.C5_RESOLUTIONS, args.pool)
+    host_pools = {}
+    pools = _frame_pools(torch, synth.C5_RESOLUTIONS, args.pool, host_pools)
     print("serving: generated %d frames per resolution in %.1fs" % (args.pool, time.time() - t0),
           file=sys.stderr, flush=True)
     budget = int((args.budget_gb or 200.0) * (1 << 30))
@@ -268,12 +289,19 @@ def bench_serving(args, modes=("batched", "per_stream"), saturating=True):
     if saturating:
         traces.append(("c5_saturating", synth.c5_sessions(**SATURATING), args.saturating_seconds))
     out = {}
+    # the served outputs of one session (the first of the smallest resolution,
+    # its first 20 frames) are checked against the oracle fed the same frames
+    small = min(traces[0][1], key=lambda x: (x.width * x.height, x.sid))
+    recorded = None
     for name, sessions, seconds in traces:
         out[name] = {}
         for mode in modes:
             srv = Server(budget_bytes=budget, max_batch=32, per_stream=mode == "per_stream",
                          tile=tuple(args.serve_tile))
-            res, _ = srv.run(sessions, pools, seconds=seconds)
+            rec_sid = small.sid if (name == "c5" and mode == "batched") else None
+            res, rec = srv.run(sessions, pools, seconds=seconds, record=rec_sid, record_frames=20)
+            if rec_sid is not None:
+                recorded = rec
             res["budget_gb"] = round(budget / (1 << 30), 2)
             res["frames_cycled_per_resolution"] = args.pool
             out[name][mode] = res
@@ -284,8 +312,12 @@ def bench_serving(args, modes=("batched", "per_stream"), saturating=True):
             del srv
             gc.collect()
             torch.cuda.empty_cache()
+    if recorded:
+        out["parity"] = serving_parity(torch, small, recorded, host_pools[(small.width, small.height)])
     if "batched" in modes and "per_stream" in modes:
         for name in out:
+            if name == "parity":
+                continue
             b, s = out[name]["batched"], out[name]["per_stream"]
             out[name]["batched_over_per_stream"] = {
                 "mpix_per_s": round(b["mpix_per_s"] / max(s["mpix_per_s"], 1e-9), 3),
@@ -305,11 +337,13 @@ def bench_batched(args, tune: bool, small: bool = True):
 
     wls = synth.c4_streams()
     t0 = time.time()
-    pools = []
+    pools, host_pools = [], []
     for wl in wls:
         src = synth.FrameSource(wl)
+        frames = [src.next() for _ in range(args.pool)]
+        host_pools.append(frames)
         pools.append([tuple(torch.from_numpy(a).cuda() for a in (f.color, f.feats, f.var, f.motion))
-                      for f in (src.next() for _ in range(args.pool))])
+                      for f in frames])
     torch.cuda.synchronize()
     print("generated %d frames for %d streams in %.1fs" % (args.pool * len(wls), len(wls),
                                                           time.time() - t0), file=sys.stderr, flush=True)
@@ -387,6 +421,28 @@ def bench_batched(args, tune: bool, small: bool = True):
                 torch.cuda.synchronize()
             small_res[name] = round(e0.elapsed_time(e1) / K, 4)
         small_res["batched_speedup"] = round(small_res["per_stream_launches"] / small_res["batched_graph"], 3)
+    # parity: fresh streams through the same batched launch over the pooled
+    # frames, every stream against the FP64 oracle fed the same frames
+    import oracle
+    fresh = [wrls.Stream(wl.width, wl.height, 8, in_dtype="f16", hip_stream=hs) for wl in wls]
+    gpu_outs = []
+    with torch.cuda.stream(ext):
+        for t in range(args.pool):
+            o_t = [torch.empty((3, wl.height, wl.width), device="cuda") for wl in wls]
+            batch.step(fresh, [p[t] for p in pools], o_t)
+            gpu_outs.append(o_t)
+    torch.cuda.synchronize()
+    par = _Parity(torch)
+    for i, wl in enumerate(wls):
+        o = oracle.Oracle(wl.width, wl.height, 8, lam=0.98)
+        for t in range(args.pool):
+            f = host_pools[i][t]
+            ref, scale = o.step(f.color, f.feats, f.var, f.motion, want_scale=True)
+            par.add(gpu_outs[t][i], ref, scale)
+        del o
+    parity = par.report()
+    parity["streams"] = len(wls)
+    del gpu_outs, fresh
     bpp = algorithmic_bytes_per_pixel(8, 2)
     b_ms = res["batched_graph"]["ms_per_round"]
     s_ms = res["per_stream_launches"]["ms_per_round"]
@@ -411,6 +467,7 @@ def bench_batched(args, tune: bool, small: bool = True):
         "batched_speedup": round(s_ms / b_ms, 4),
         "wall_ms_per_round": {k: round(v["wall_ms_per_round"], 4) for k, v in res.items()},
         "small_frames_64x320x240_ms_per_round": small_res,
+        "parity": parity,
     }
 
 
@@ -600,14 +657,15 @@ def bench_step(args, workload: str, with_cpu: bool, parity_frames=None, with_ble
                 g = gpu.step(*dev_frames[t])
                 par.add(g, ref, scale)
                 if o32 is not None and t < n_unrounded:
-                    par32.add(g, step_oracle(o32, f, unrounded=True), None)
+                    par32.add(g, *step_oracle(o32, f, want_scale=True, unrounded=True))
         del o, o32
         gpu.close()
         p = par.report()
         p["reference"] = "FP64 oracle on the same inputs (FP16-rounded where the workload is FP16)"
         if n_unrounded:
             p["vs_unrounded_fp32_inputs"] = {
-                "frames": par32.frames, "y_relative_max": float("%.3g" % par32.y_rel),
+                "frames": par32.frames, "g1_max": float("%.3g" % par32.g1),
+                "y_relative_max": float("%.3g" % par32.y_rel),
                 "note": "GPU on FP16 inputs against the oracle fed the unrounded FP32 inputs: "
                         "measures the binary16 rounding of colour and features"}
         res["parity"] = p

@@ -50,5 +50,52 @@ def needs_build() -> bool:
     return any(os.path.getmtime(p) > t for p in deps)
 
 
+FIELDS = (("VGPRs", "VGPRs"), ("AGPRs", "AGPRs"), ("TotalSGPRs", "SGPRs"),
+          ("VGPRs Spill", "VGPR spill"), ("SGPRs Spill", "SGPR spill"),
+          ("ScratchSize [bytes/lane]", "scratch B/lane"), ("Occupancy [waves/SIMD]", "waves/SIMD"),
+          ("LDS Size [bytes/block]", "static LDS B"))
+
+
+def resource_usage() -> str:
+    """The compiler's resource use of every kernel (registers, spills,
+    scratch, occupancy, static LDS), from a device-only compile of the
+    kernels with the library's flags and -Rpass-analysis=kernel-resource-usage;
+    a Markdown table, kernels demangled."""
+    import re
+    src = os.path.join(CSRC, "wrls_kernels.hip")
+    out = os.path.join("/tmp", "wrls_resource_usage_%d.o" % os.getpid())
+    cmd = [hipcc()] + [f for f in HIPCC_FLAGS if f != "-shared"] + [
+        "--offload-device-only", "-c", "-Rpass-analysis=kernel-resource-usage",
+        "-I", INCLUDE, "-I", CSRC, "-o", out, src]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stderr)
+        raise RuntimeError("hipcc failed")
+    if os.path.exists(out):
+        os.remove(out)
+    rows, cur = [], None
+    for line in r.stderr.splitlines():
+        m = re.search(r"remark: Function Name: (\S+)", line)
+        if m:
+            cur = {"name": m.group(1)}
+            rows.append(cur)
+            continue
+        m = re.search(r"remark: +([^:]+): (\S+) \[-Rpass", line)
+        if m and cur is not None:
+            cur[m.group(1).strip()] = m.group(2)
+    # _Float16 mangles as DF16_, which c++filt does not know: print it as half
+    names = "\n".join(row["name"].replace("DF16_", "Dh") for row in rows)
+    dem = subprocess.run(["c++filt"], input=names, capture_output=True, text=True).stdout.splitlines()
+    lines = ["| kernel | " + " | ".join(h for _, h in FIELDS) + " |",
+             "|---|" + "---|" * len(FIELDS)]
+    for row, name in zip(rows, dem):
+        name = name.replace("wrls::(anonymous namespace)::", "").split("(")[0]
+        lines.append("| `%s` | " % name + " | ".join(row.get(k, "") for k, _ in FIELDS) + " |")
+    return "\n".join(lines)
+
+
 if __name__ == "__main__":
-    print(build(verbose=True))
+    if len(sys.argv) > 1 and sys.argv[1] == "--resource-usage":
+        print(resource_usage())
+    else:
+        print(build(verbose=True))

@@ -749,23 +749,43 @@ constexpr int kBlendRN = kBlendRW * kBlendRH;
 constexpr int kBlendThreads = kBlendTW * kBlendTH / kBlendRPT;
 constexpr int kBlendSlots = (kBlendRN + kBlendThreads - 1) / kBlendThreads;
 constexpr int kBlendK = 2 * kBlendR + 1;  // window side
+// Blend tiles run in vertical strips of this many tiles (0: the full image
+// width), so that a tile's top halo rows, which the tile above also read,
+// are still in L2.  Strips of 3 and 8 tiles cut 4K reads but timed the same
+// as the full width (4K d = 10: 421-425 us against 422), and 2% slower at
+// 1080p and in paper mode.
+constexpr int kBlendStripTiles = 0;
 
 // The occupancy hint caps registers: left alone, the scheduler keeps most of
 // a channel's LDS reads in flight and needs 168+ VGPRs at d = 8.
 template <int D, typename InT, bool PAPER>
 __global__ void __launch_bounds__(kBlendThreads)
-__attribute__((amdgpu_waves_per_eu(D <= 1 ? 5 : (D <= 7 ? 4 : (D <= 9 ? 3 : 2)))))
+__attribute__((amdgpu_waves_per_eu(D <= 7 ? 4 : (D <= 9 ? 3 : 2))))
 blend_kernel(const BlendArgs a)
 {
     constexpr int RPT = kBlendRPT;
     constexpr int NS = state_floats(D) + (PAPER ? 3 : 0);
     constexpr int NG = (D + 3) / 4;  // groups of four beta entries
-    __shared__ float4 s_guide[kBlendRN];
-    __shared__ float4 s_beta[NG][kBlendRN];
+    // The guide is read only while the weights are computed, before the
+    // channel loop.  With three groups of beta entries (d >= 9) it shares
+    // LDS with the beta staging, a barrier separating the two uses: a
+    // workgroup holds 39 KB instead of 52 KB, so four fit on a compute unit
+    // instead of three (4K d = 10: 466 -> 422 us).  With fewer groups the
+    // registers bound occupancy anyway and the extra barrier costs (paper
+    // mode 44.7 -> 47.7 us), so the guide has its own LDS.
+    constexpr bool kShareGuide = NG >= 3;
+    __shared__ float4 s_lds[(kShareGuide ? NG : NG + 1) * kBlendRN];
+    float4 *const s_guide = kShareGuide ? s_lds : s_lds + NG * kBlendRN;
 
     const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
-    const int tyi = tile / a.tiles_x;
-    const int x0 = (tile - tyi * a.tiles_x) * kBlendTW, y0 = tyi * kBlendTH;
+    int txi, tyi;
+    if constexpr (kBlendStripTiles > 0) {
+        tile_coords(tile, a.tiles_x, a.tiles_y, min(kBlendStripTiles, a.tiles_x), txi, tyi);
+    } else {
+        tyi = tile / a.tiles_x;
+        txi = tile - tyi * a.tiles_x;
+    }
+    const int x0 = txi * kBlendTW, y0 = tyi * kBlendTH;
     const int tid = (int)threadIdx.x;
     const int lx = tid % kBlendTW, ly = (tid / kBlendTW) * RPT;  // first of the thread's rows
     const int x = x0 + lx;
@@ -936,7 +956,7 @@ blend_kernel(const BlendArgs a)
             if (sl < kBlendRN)
 #pragma unroll
                 for (int gq = 0; gq < NG; gq++)
-                    s_beta[gq][sl] = make_float4(nx[r][4 * gq], nx[r][4 * gq + 1], nx[r][4 * gq + 2],
+                    s_lds[gq * kBlendRN + sl] = make_float4(nx[r][4 * gq], nx[r][4 * gq + 1], nx[r][4 * gq + 2],
                                                  nx[r][4 * gq + 3]);
         }
     };
@@ -948,7 +968,8 @@ blend_kernel(const BlendArgs a)
     // LDS reads and runs out of registers
 #pragma unroll 1
     for (int c = 0; c < 3; c++) {
-        if (c > 0) __syncthreads();  // the previous channel's reads are done
+        // the previous channel's reads (the guide's, before channel 0) are done
+        if (c > 0 || kShareGuide) __syncthreads();
         if constexpr (kPipelined) {
             stage(AllSlots0{}, AllSlots1{});
             fetch_channel(c + 1, AllSlots0{}, AllSlots1{});
@@ -983,7 +1004,7 @@ blend_kernel(const BlendArgs a)
             for (int hr = 0; hr < RPT + 2 * kBlendR; hr++)
 #pragma unroll
                 for (int dx = -kBlendR; dx <= kBlendR; dx++) {
-                    const float4 bv = s_beta[gq][(ly + hr) * kBlendRW + lx + kBlendR + dx];
+                    const float4 bv = s_lds[gq * kBlendRN + (ly + hr) * kBlendRW + lx + kBlendR + dx];
                     const float b4[4] = {bv.x, bv.y, bv.z, bv.w};
 #pragma unroll
                     for (int r = 0; r < RPT; r++) {

@@ -262,11 +262,12 @@ class Server:
         self.created.pop(s.sid, None)
 
     def run(self, sessions, frame_pools, seconds: float, record: Optional[int] = None,
-            poll: float = 2e-4):
+            poll: float = 2e-4, record_frames: Optional[int] = None):
         """sessions: synth.Session list; frame_pools[(w, h)]: list of device
         frame tuples, cycled.  Runs until `seconds` have passed or every
         session is served.  record: sid whose outputs are kept (host copies)
-        for the alone-vs-mix check."""
+        for the alone-vs-mix and oracle checks, its first record_frames
+        frames (None: all)."""
         torch = self.torch
         pending = sorted([SessionState(x.sid, x.width, x.height, x.fps, x.arrival,
                                        x.arrival + x.duration) for x in sessions],
@@ -284,7 +285,7 @@ class Server:
             for s in members:
                 s.latencies.append(t_done - s.frame_time(s.next_frame - 1))
                 s.in_flight = False
-                if s.sid == record:
+                if s.sid == record and (record_frames is None or len(recorded) < record_frames):
                     recorded.append(self.outs[s.sid].cpu())
             pixels += npx
 

@@ -24,6 +24,8 @@ def modes(d_features: int):
         ("wrls_features", d_features, dict(wmode=oracle.W_INVVAR, delta=math.exp(-synth.VAR_MU))),
         ("rls_temporal_feature", 4, dict(wmode=oracle.W_PAPER, h_bw=1e3)),
         ("wrls_temporal_feature", 4, dict(wmode=oracle.W_PAPER)),
+        ("wrls_features_auto_lambda", d_features, dict(wmode=oracle.W_INVVAR, delta=math.exp(-synth.VAR_MU),
+                                                       sigma0=60.0, lam_min=0.5)),
     ]
 
 

@@ -22,7 +22,8 @@ def test_gpu_ablation_matches_oracle():
     log("ablation gpu %s" % gpu)
     log("ablation oracle %s" % ref)
     assert abs(gpu["input"]["psnr_db"] - ref["input"]["psnr_db"]) < 0.01
-    for name in ("rls_features", "wrls_features", "rls_temporal_feature", "wrls_temporal_feature"):
+    for name in ("rls_features", "wrls_features", "rls_temporal_feature", "wrls_temporal_feature",
+                 "wrls_features_auto_lambda"):
         for key in ("psnr_db", "psnr_blend_db"):
             assert abs(gpu[name][key] - ref[name][key]) < 0.01, (name, key, gpu[name][key], ref[name][key])
     assert gpu["wrls_temporal_feature"]["psnr_db"] > gpu["rls_temporal_feature"]["psnr_db"]
