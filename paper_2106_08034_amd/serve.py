@@ -13,6 +13,9 @@ cross-stream waits and lets the two in-flight steps overlap on the device.
 Latency is measured on the host from a frame's arrival to the moment its
 step is seen complete.
 
+A batch of one frame goes out as a plain wrls_step launch: the batched
+step's table staging and graph replay would only add latency to it.
+
 The per-stream baseline serves the same trace with one wrls_step launch per
 ready frame (no batching), alternating between the same two HIP streams,
 with up to two launches per batch slot in flight.
@@ -206,10 +209,8 @@ class Server:
         # stream (their work is complete by then, so the close need not wait)
         self.idle = torch.cuda.Stream()
         self.sched = Scheduler(budget_bytes, self.footprint, max_batch)
-        if per_stream and tile is not None:
-            self.stream_tile = tile
-        else:
-            self.stream_tile = None
+        # single-frame launches use the batch's tile shape too
+        self.stream_tile = tile
         self.streams: Dict[int, object] = {}
         self.outs: Dict[int, object] = {}
         self.created: Dict[int, object] = {}   # sid -> event after its initialisation
@@ -320,7 +321,7 @@ class Server:
                 for s in members:
                     pool = frame_pools[(s.width, s.height)]
                     frames.append(pool[s.next_frame % len(pool)])
-                if self.per_stream:
+                if self.per_stream or len(members) == 1:
                     st = self.streams[members[0].sid]
                     self.wrls.wrls_set_hip_stream(st.handle, self.hip[bi].cuda_stream)
                     st.step(*frames[0], out=self.outs[members[0].sid])
