@@ -236,10 +236,11 @@ def run_ablation(width: int, height: int, frames: int, warm: int, sigma_s: float
 
 def _frame_pools(torch, shapes, count, host=None):
     """Device frames of the serving recipe, `count` per (width, height);
-    host, if given, receives the host frames of the smallest resolution."""
+    host, if given, receives the host frames of the smallest 32-session
+    trace resolution."""
     import synth
     pools = {}
-    smallest = min(shapes, key=lambda s: s[0] * s[1])
+    smallest = min(synth.C5_RESOLUTIONS, key=lambda s: s[0] * s[1])
     for i, (w, h) in enumerate(shapes):
         src = synth.FrameSource(synth.c5_frame_pool(w, h, count), stream=i)
         frames = [src.next() for _ in range(count)]
@@ -277,20 +278,24 @@ def bench_serving(args, modes=("batched", "per_stream"), saturating=True):
     import torch
 
     import synth
-    from paper_2106_08034_amd.serve import SATURATING, Server
+    from paper_2106_08034_amd.serve import SATURATING, SMALL_FRAMES, Server
 
     t0 = time.time()
     host_pools = {}
-    pools = _frame_pools(torch, synth.C5_RESOLUTIONS, args.pool, host_pools)
+    shapes = list(synth.C5_RESOLUTIONS) + [r for r in SMALL_FRAMES["resolutions"]
+                                           if r not in synth.C5_RESOLUTIONS]
+    pools = _frame_pools(torch, shapes, args.pool, host_pools)
     print("serving: generated %d frames per resolution in %.1fs" % (args.pool, time.time() - t0),
           file=sys.stderr, flush=True)
     budget = int((args.budget_gb or 200.0) * (1 << 30))
     traces = [("c5", synth.c5_sessions(), args.serve_seconds)]
     if saturating:
         traces.append(("c5_saturating", synth.c5_sessions(**SATURATING), args.saturating_seconds))
+        traces.append(("small_frames", synth.c5_sessions(**SMALL_FRAMES), args.saturating_seconds))
     out = {}
-    # the served outputs of one session (the first of the smallest resolution,
-    # its first 20 frames) are checked against the oracle fed the same frames
+    # the served outputs of one session (the first of the smallest resolution
+    # of the plain trace, its first 20 frames) are checked against the oracle
+    # fed the same frames
     small = min(traces[0][1], key=lambda x: (x.width * x.height, x.sid))
     recorded = None
     for name, sessions, seconds in traces:

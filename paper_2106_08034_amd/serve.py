@@ -38,6 +38,13 @@ ALIGN = 256
 # inputs (keyword arguments of synth.c5_sessions).
 SATURATING = dict(rate=16.0, fps_range=(120.0, 240.0))
 
+# A launch-bound variant: the same 32 sessions at small resolutions and high
+# frame rates (8.5-10 thousand frames per second in all from t = 3 s on,
+# 1.2-1.5 Gpx/s): here the cost per launch, not the GPU's bandwidth, decides
+# what a server delivers.
+SMALL_FRAMES = dict(rate=16.0, resolutions=((320, 240), (480, 270), (640, 360)),
+                    fps_range=(240.0, 480.0))
+
 
 class Arena:
     """First-fit allocator of byte ranges in [0, size), ALIGN-aligned, with

@@ -29,7 +29,11 @@ def _replay_alone(sess, pool, n):
     return outs
 
 
-def test_served_session_equals_alone_bitwise():
+@pytest.mark.parametrize("per_stream", [False, True])
+def test_served_session_equals_alone_bitwise(per_stream):
+    """Batched serving (one-frame batches go out as plain launches) and the
+    per-stream baseline: a session's outputs are those of the session run
+    alone, bitwise, and match the oracle."""
     from paper_2106_08034_amd.serve import Server
     shapes = [(160, 96), (224, 128), (96, 64)]
     sessions = [synth.Session(sid=i, width=shapes[i % 3][0], height=shapes[i % 3][1],
@@ -37,12 +41,15 @@ def test_served_session_equals_alone_bitwise():
                 for i in range(8)]
     host = {}
     pools = _pools(shapes, host=host)
-    srv = Server(budget_bytes=256 << 20, max_batch=8)
-    log("case serve 8 small sessions")
+    srv = Server(budget_bytes=256 << 20, max_batch=8, per_stream=per_stream)
+    log("case serve 8 small sessions, per_stream=%s" % per_stream)
     res, rec = srv.run(sessions, pools, seconds=5.0, record=3)
     log("serve result %s" % res)
     assert res["sessions_served"] == 8 and res["frames"] > 100
     assert len(rec) >= 20
+    assert res["mode"] == ("per_stream_launches" if per_stream else "batched")
+    if per_stream:
+        assert res["steps"] == res["frames"]   # one launch per frame
     key = (sessions[3].width, sessions[3].height)
     alone = _replay_alone(sessions[3], pools[key], len(rec))
     for k, (a, b) in enumerate(zip(alone, rec)):
@@ -59,6 +66,7 @@ def test_served_session_equals_alone_bitwise():
         worst = max(worst, e)
         assert e <= G1_TOL, (k, e)
     log("served session vs oracle over %d frames: worst G1 %.3g" % (len(rec), worst))
+    srv.close()
 
 
 def test_budget_admission_queues_sessions():
