@@ -273,8 +273,10 @@ def bench_serving(args, modes=("batched", "per_stream"), saturating=True):
     HBM-budget admission, continuous batching with two steps in flight, or
     the per-stream baseline (one launch per frame).  With `saturating`, the
     same sessions again at 16 arrivals/s and 120-240 Hz (more pixels per
-    second than the GPU steps) for args.saturating_seconds.  Returns
-    {trace: {mode: report}} (Mpix/s, p50/p99 latency, ...)."""
+    second than the GPU steps), also batched with admission by pixel rate,
+    and at small resolutions and 240-480 Hz (launch-bound), each for
+    args.saturating_seconds.  Returns {trace: {mode: report}} (Mpix/s,
+    p50/p99 latency, ...) and the oracle check of one served session."""
     import torch
 
     import synth
@@ -292,6 +294,9 @@ def bench_serving(args, modes=("batched", "per_stream"), saturating=True):
     if saturating:
         traces.append(("c5_saturating", synth.c5_sessions(**SATURATING), args.saturating_seconds))
         traces.append(("small_frames", synth.c5_sessions(**SMALL_FRAMES), args.saturating_seconds))
+    # rate-limited admission on the saturating trace: sessions wait for
+    # admission instead of their frames queueing behind a backlog
+    rate_budget = args.serve_rate_gpx * 1e9 if args.serve_rate_gpx > 0 else None
     out = {}
     # the served outputs of one session (the first of the smallest resolution
     # of the plain trace, its first 20 frames) are checked against the oracle
@@ -317,6 +322,22 @@ def bench_serving(args, modes=("batched", "per_stream"), saturating=True):
             del srv
             gc.collect()
             torch.cuda.empty_cache()
+        if name == "c5_saturating" and rate_budget is not None:
+            for mode in modes:
+                srv = Server(budget_bytes=budget, max_batch=32, tile=tuple(args.serve_tile),
+                             rate_budget=rate_budget, per_stream=mode == "per_stream")
+                res, _ = srv.run(sessions, pools, seconds=seconds)
+                res["budget_gb"] = round(budget / (1 << 30), 2)
+                out[name + "_rate_admission"] = out.get(name + "_rate_admission", {})
+                out[name + "_rate_admission"][mode] = res
+                print("serving %s %s with rate admission: %.0f Mpix/s, p50 %.3f ms, p99 %.3f ms" % (
+                    name, mode, res["mpix_per_s"], res["p50_ms"], res["p99_ms"]), file=sys.stderr,
+                    flush=True)
+                torch.cuda.synchronize()
+                srv.close()
+                del srv
+                gc.collect()
+                torch.cuda.empty_cache()
     if recorded:
         out["parity"] = serving_parity(torch, small, recorded, host_pools[(small.width, small.height)])
     if "batched" in modes and "per_stream" in modes:
@@ -689,7 +710,9 @@ def bench_step(args, workload: str, with_cpu: bool, parity_frames=None, with_ble
             cpu = {"value": round(frames_done * npix / cpu_s / 1e6, 3), "unit": "Mpix/s",
                    "cores": cores, "cpu_model": cpu_model(), "kind": "oracle",
                    "sample": "FP64 C oracle (OpenMP over rows), %d pass(es) over the first %d frames "
-                             "of the same %s sequence, %.1f s" % (passes, n_cpu, wl.name, cpu_s)}
+                             "of the same %s sequence, %.1f s (the first pass also returns each "
+                             "output's term magnitude, the parity reference)" % (passes, n_cpu, wl.name,
+                                                                                  cpu_s)}
             # the same oracle on one thread, over the first frame(s)
             oracle.set_threads(1)
             n1 = min(args.single_thread_frames, n_cpu)
@@ -729,6 +752,9 @@ def main():
                     help="wall seconds of serving the saturating trace, per mode")
     ap.add_argument("--budget-gb", type=float, default=0.0,
                     help="serving: HBM budget for session state (0: 200 GB)")
+    ap.add_argument("--serve-rate-gpx", type=float, default=8.0,
+                    help="saturating trace: also serve it batched with admission limited to this "
+                         "many Gpx/s offered (0: skip)")
     ap.add_argument("--pool", type=int, default=0,
                     help="distinct frames generated per stream (c4) or per resolution "
                          "(serving), cycled (0: 4 in the default run, 60 with --workload c5)")

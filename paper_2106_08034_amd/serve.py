@@ -4,12 +4,12 @@ Each session (a viewer) owns a wRLS stream whose state stays resident in
 HBM for the session's lifetime.  Sessions are admitted while their device
 footprint fits a fixed HBM budget (an arena carved once from device memory,
 so admission never allocates); the others wait in arrival order.  Frames
-arrive per session at its frame rate; the scheduler packs every session's
-oldest ready frame into one batched step (continuous batching: sessions
-join and leave between steps) and keeps two steps in flight on two HIP
-streams, so a new step is enqueued while the previous one runs.  A session
-has at most one frame in flight, which orders its frames without
-cross-stream waits and lets the two in-flight steps overlap on the device.
+arrive per session at its frame rate; every tick the scheduler packs the
+sessions' due frames (oldest first, at most max_batch) into one batched step
+(continuous batching: sessions join and leave between steps), which goes out
+at once, on one of two HIP streams, with up to 2 * max_batch launches in
+flight.  A session has at most one frame in flight, which orders its frames
+without cross-stream waits and lets the launches overlap on the device.
 Latency is measured on the host from a frame's arrival to the moment its
 step is seen complete.
 
@@ -18,7 +18,7 @@ step's table staging and graph replay would only add latency to it.
 
 The per-stream baseline serves the same trace with one wrls_step launch per
 ready frame (no batching), alternating between the same two HIP streams,
-with up to two launches per batch slot in flight.
+with the same number of launches in flight.
 
 The scheduling rules (arena, admission, batch composition) are plain
 Python, independent of the GPU; Server drives them against the library.
@@ -114,32 +114,47 @@ class SessionState:
 
 
 class Scheduler:
-    """Admission by device footprint and batch composition (no GPU)."""
+    """Admission by device footprint (and optionally by pixel rate) and batch
+    composition (no GPU).  rate_budget: pixels per second the admitted
+    sessions may offer together (their width x height x frame rate); None
+    admits by memory alone, so an offered load above the GPU's rate queues
+    frames without bound."""
 
-    def __init__(self, budget: int, footprint, max_batch: int):
+    def __init__(self, budget: int, footprint, max_batch: int, rate_budget: Optional[float] = None):
         self.arena = Arena(budget)
         self.footprint = footprint      # (width, height) -> bytes
         self.max_batch = max_batch
+        self.rate_budget = rate_budget
+        self.rate = 0.0                 # pixels per second the active sessions offer
         self.waiting: List[SessionState] = []
         self.active: List[SessionState] = []
         self.done: List[SessionState] = []
         self.rejected: List[SessionState] = []
 
+    @staticmethod
+    def offered(s: SessionState) -> float:
+        return float(s.width * s.height) * s.fps
+
     def arrive(self, s: SessionState):
-        if self.footprint(s.width, s.height) > self.arena.size:
+        too_fast = self.rate_budget is not None and self.offered(s) > self.rate_budget
+        if self.footprint(s.width, s.height) > self.arena.size or too_fast:
             self.rejected.append(s)       # can never fit
         else:
             self.waiting.append(s)
 
     def admit(self, now: float) -> List[SessionState]:
-        """Admits waiting sessions in arrival order while they fit."""
+        """Admits waiting sessions in arrival order while they fit (memory,
+        and the pixel rate when it is budgeted)."""
         admitted = []
         while self.waiting:
             s = self.waiting[0]
+            if self.rate_budget is not None and self.rate + self.offered(s) > self.rate_budget:
+                break                     # head-of-line: keep arrival order
             off = self.arena.alloc(self.footprint(s.width, s.height))
             if off is None:
-                break                     # head-of-line: keep arrival order
+                break
             self.waiting.pop(0)
+            self.rate += self.offered(s)
             s.offset = off
             s.admitted_at = now
             s.end = now + (s.end - s.arrival)   # a session lasts its duration once served
@@ -155,17 +170,22 @@ class Scheduler:
         return ready[: self.max_batch]
 
     def next_launches(self, now: float, per_stream: bool, slots: int) -> List[List[SessionState]]:
-        """The launches to issue now, given `slots` free launch slots:
-        batched, one launch of next_batch(now); per stream, one launch per
-        session of next_batch(now), at most `slots` of them."""
+        """The launches to issue now, given `slots` free launch slots, for the
+        sessions of next_batch(now): per stream, one launch per session;
+        batched, one launch per resolution among them (in order of each
+        resolution's oldest due frame).  A batched launch completes all its
+        frames together, so a small frame batched with a large one would
+        wait for it; frames of one size finish together either way.  At
+        most `slots` launches."""
         if slots <= 0:
             return []
         members = self.next_batch(now)
-        if not members:
-            return []
         if per_stream:
             return [[s] for s in members[:slots]]
-        return [members]
+        groups: Dict[Tuple[int, int], List[SessionState]] = {}
+        for s in members:
+            groups.setdefault((s.width, s.height), []).append(s)
+        return list(groups.values())[:slots]
 
     def retire(self, now: float) -> List[SessionState]:
         """Ends sessions past their end with nothing in flight; frees memory."""
@@ -175,6 +195,7 @@ class Scheduler:
             s.finished = True
             self.active.remove(s)
             self.arena.release(s.offset)
+            self.rate -= self.offered(s)
             self.done.append(s)
         return gone
 
@@ -194,28 +215,36 @@ class Server:
 
     def __init__(self, budget_bytes: int, d: int = 8, in_dtype: str = "f16", max_batch: int = 32,
                  lam: float = 0.98, tile: Optional[Tuple[int, int, int]] = None,
-                 per_stream: bool = False):
+                 per_stream: bool = False, rate_budget: Optional[float] = None):
         """per_stream: serve with one wrls_step launch per frame (the
-        unbatched baseline) instead of batched steps."""
+        unbatched baseline) instead of batched steps.  rate_budget: admit
+        sessions only while their offered pixels per second fit it (None:
+        by memory alone)."""
         import torch
 
         from . import wrls
         self.torch, self.wrls = torch, wrls
         self.d, self.in_dtype, self.lam = d, in_dtype, lam
         self.per_stream = per_stream
-        # launches in flight: two batched steps, or two per batch slot
-        self.max_inflight = 2 * max_batch if per_stream else 2
+        # launches in flight, batched or not: two per batch slot, so that a
+        # due frame never waits on the host for the GPU to finish others
+        self.max_inflight = 2 * max_batch
         self.arena_mem = torch.empty(budget_bytes + ALIGN, dtype=torch.uint8, device="cuda")
         self.delta = (-self.arena_mem.data_ptr()) % ALIGN   # first aligned byte
-        self.batches = [wrls.Batch(max_batch, d, in_dtype) for _ in range(2)]
-        self.hip = [torch.cuda.ExternalStream(b.hip_stream) for b in self.batches]
+        # two HIP streams (torch's, which outlive every context), and enough
+        # batch contexts on them that each in-flight launch has its own frame
+        # table (a context holds two): a new batched step never waits for a
+        # table to come free
+        self.hip = [torch.cuda.Stream(), torch.cuda.Stream()]
+        self.batches = [wrls.Batch(max_batch, d, in_dtype, hip_stream=self.hip[k % 2].cuda_stream)
+                        for k in range(self.max_inflight // 2)]
         if tile is not None:
             for b in self.batches:
                 b.set_tile(*tile)
         # handles are created on hip[0]; closed after moving them to an idle
         # stream (their work is complete by then, so the close need not wait)
         self.idle = torch.cuda.Stream()
-        self.sched = Scheduler(budget_bytes, self.footprint, max_batch)
+        self.sched = Scheduler(budget_bytes, self.footprint, max_batch, rate_budget)
         # single-frame launches use the batch's tile shape too
         self.stream_tile = tile
         self.streams: Dict[int, object] = {}
@@ -251,7 +280,7 @@ class Server:
         ptr = self.arena_mem.data_ptr() + start
         self.streams[s.sid] = wrls.Stream(s.width, s.height, self.d, lam=self.lam,
                                           in_dtype=self.in_dtype,
-                                          hip_stream=self.batches[0].hip_stream,
+                                          hip_stream=self.hip[0].cuda_stream,
                                           device_mem=(ptr, nstate))
         if self.stream_tile is not None:
             self.streams[s.sid].set_tile(self.stream_tile[0], self.stream_tile[1], 0)
@@ -283,6 +312,7 @@ class Server:
         inflight = []          # (event, members, pixels)
         recorded = []
         steps = 0
+        nbatched = 0           # batched launches so far
         pixels = 0
         max_active = 0
         t0 = time.perf_counter()
@@ -319,7 +349,13 @@ class Server:
             launches = self.sched.next_launches(now, self.per_stream,
                                                 self.max_inflight - len(inflight))
             for members in launches:
-                bi = steps % 2
+                batched = not self.per_stream and len(members) > 1
+                if batched:   # the next context; it runs on its own stream
+                    ctx = self.batches[nbatched % len(self.batches)]
+                    bi = (nbatched % len(self.batches)) % 2
+                    nbatched += 1
+                else:
+                    bi = steps % 2
                 for s in members:   # a new session's initialisation ran on hip[0]
                     ev = self.created.pop(s.sid, None)
                     if ev is not None and bi != 0:
@@ -328,13 +364,13 @@ class Server:
                 for s in members:
                     pool = frame_pools[(s.width, s.height)]
                     frames.append(pool[s.next_frame % len(pool)])
-                if self.per_stream or len(members) == 1:
+                if batched:
+                    ctx.step([self.streams[s.sid] for s in members], frames,
+                             [self.outs[s.sid] for s in members])
+                else:
                     st = self.streams[members[0].sid]
                     self.wrls.wrls_set_hip_stream(st.handle, self.hip[bi].cuda_stream)
                     st.step(*frames[0], out=self.outs[members[0].sid])
-                else:
-                    self.batches[bi].step([self.streams[s.sid] for s in members], frames,
-                                          [self.outs[s.sid] for s in members])
                 ev = torch.cuda.Event()
                 ev.record(self.hip[bi])
                 for s in members:
@@ -369,6 +405,8 @@ class Server:
             "sessions_waiting_at_end": len(self.sched.waiting),
             "sessions_rejected": len(self.sched.rejected),
             "max_concurrent": max_active,
+            "rate_budget_gpx_s": (round(self.sched.rate_budget / 1e9, 3)
+                                  if self.sched.rate_budget is not None else None),
             # arrival to admission: grows when the HBM budget makes sessions queue
             "admission_wait_p50_ms": round(percentile(waits, 50) * 1e3, 3) if waits else None,
             "admission_wait_max_ms": round(max(waits) * 1e3, 3) if waits else None,

@@ -116,3 +116,44 @@ def test_saturating_trace_offers_more_than_the_step_rate():
     sat = synth.c5_sessions(**SATURATING)
     assert min(offered(sat, t) for t in (3, 5, 8, 10)) > 11e9
     assert max(offered(plain, t) for t in range(16)) < 4.5e9
+
+
+def test_batched_launches_group_by_resolution():
+    """Batched, the due frames go out as one launch per resolution, in the
+    order of each resolution's oldest due frame, within the free slots."""
+    sch = Scheduler(budget=10 ** 9, footprint=lambda w, h: 1000, max_batch=8)
+    ss = [_sess(0, 100, 50, fps=100), _sess(1, 200, 100, fps=100), _sess(2, 100, 50, fps=100),
+          _sess(3, 300, 100, fps=100), _sess(4, 200, 100, fps=100)]
+    for s in ss:
+        sch.arrive(s)
+    sch.admit(0.0)
+    ss[0].next_frame = 2           # due at 0.02 s, after the others (0.01 s)
+    for s in ss[1:]:
+        s.next_frame = 1
+    got = [[s.sid for s in m] for m in sch.next_launches(0.03, per_stream=False, slots=8)]
+    assert got == [[1, 4], [2, 0], [3]]
+    assert [[s.sid for s in m] for m in sch.next_launches(0.03, False, 2)] == [[1, 4], [2, 0]]
+    assert len(sch.next_launches(0.03, True, 8)) == 5
+
+
+def test_admission_by_pixel_rate():
+    """With a pixel-rate budget, a session is admitted only while the
+    admitted sessions' width x height x fps stays within it (arrival order
+    kept); retiring a session frees its rate; a session offering more than
+    the whole budget is rejected."""
+    sch = Scheduler(budget=10 ** 12, footprint=lambda w, h: 1000, max_batch=8, rate_budget=3.0e6)
+    a = _sess(0, 100, 100, fps=100)      # 1.0 Mpx/s
+    b = _sess(1, 100, 100, fps=150)      # 1.5 Mpx/s
+    c = _sess(2, 100, 100, fps=100)      # 1.0 Mpx/s: waits for a or b
+    d = _sess(3, 100, 100, fps=10)       # 0.1 Mpx/s: fits, but waits behind c
+    huge = _sess(4, 200, 200, fps=100)   # 4.0 Mpx/s: never fits
+    for s in (a, b, c, d, huge):
+        sch.arrive(s)
+    assert sch.rejected == [huge]
+    assert [s.sid for s in sch.admit(0.0)] == [0, 1]
+    assert sch.rate == pytest.approx(2.5e6)
+    a.next_frame = 1000
+    assert [s.sid for s in sch.retire(10.0)] == [0]
+    assert sch.rate == pytest.approx(1.5e6)
+    assert [s.sid for s in sch.admit(10.0)] == [2, 3]
+    assert sch.rate == pytest.approx(2.6e6)
