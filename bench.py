@@ -459,15 +459,23 @@ def bench_batched(args, tune: bool, small: bool = True):
             gpu_outs.append(o_t)
     torch.cuda.synchronize()
     par = _Parity(torch)
+    cpu_s = 0.0
     for i, wl in enumerate(wls):
         o = oracle.Oracle(wl.width, wl.height, 8, lam=0.98)
         for t in range(args.pool):
             f = host_pools[i][t]
+            tc = time.perf_counter()
             ref, scale = o.step(f.color, f.feats, f.var, f.motion, want_scale=True)
+            cpu_s += time.perf_counter() - tc
             par.add(gpu_outs[t][i], ref, scale)
         del o
     parity = par.report()
     parity["streams"] = len(wls)
+    cpu = {"value": round(npix * args.pool / cpu_s / 1e6, 3), "unit": "Mpix/s", "cores": oracle.threads(),
+           "cpu_model": cpu_model(), "kind": "oracle",
+           "sample": "FP64 C oracle (OpenMP over rows), the first %d frames of each of the %d streams "
+                     "(the parity pass, which also returns each output's term magnitude), %.1f s"
+                     % (args.pool, len(wls), cpu_s)}
     del gpu_outs, fresh
     bpp = algorithmic_bytes_per_pixel(8, 2)
     b_ms = res["batched_graph"]["ms_per_round"]
@@ -494,6 +502,7 @@ def bench_batched(args, tune: bool, small: bool = True):
         "wall_ms_per_round": {k: round(v["wall_ms_per_round"], 4) for k, v in res.items()},
         "small_frames_64x320x240_ms_per_round": small_res,
         "parity": parity,
+        "cpu_baseline": cpu,
     }
 
 
@@ -817,7 +826,7 @@ def main():
                     ms_per_step=r["batched"]["ms_per_round"], dtype="f32 (f16 inputs)",
                     config={"workload": r["workload"]}, roofline=dict(r["batched"]["roofline"],
                                                                       traffic=None),
-                    c4=r, cpu_baseline=None)
+                    c4=r, cpu_baseline=r["cpu_baseline"])
         print(json.dumps(line), flush=True)
         return
     if args.workload in ("ablation", "ablation_c3"):

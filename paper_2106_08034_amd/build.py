@@ -56,13 +56,14 @@ FIELDS = (("VGPRs", "VGPRs"), ("AGPRs", "AGPRs"), ("TotalSGPRs", "SGPRs"),
           ("LDS Size [bytes/block]", "static LDS B"))
 
 
-def resource_usage() -> str:
+def resource_usage(src: str = "") -> str:
     """The compiler's resource use of every kernel (registers, spills,
     scratch, occupancy, static LDS), from a device-only compile of the
-    kernels with the library's flags and -Rpass-analysis=kernel-resource-usage;
+    kernels (or of another source file `src` that includes the same headers)
+    with the library's flags and -Rpass-analysis=kernel-resource-usage;
     a Markdown table, kernels demangled."""
     import re
-    src = os.path.join(CSRC, "wrls_kernels.hip")
+    src = src or os.path.join(CSRC, "wrls_kernels.hip")
     out = os.path.join("/tmp", "wrls_resource_usage_%d.o" % os.getpid())
     cmd = [hipcc()] + [f for f in HIPCC_FLAGS if f != "-shared"] + [
         "--offload-device-only", "-c", "-Rpass-analysis=kernel-resource-usage",

@@ -17,6 +17,7 @@
 // handed to the eight XCDs in contiguous ranges so neighbouring tiles, which
 // share source rows, meet in one L2.
 #include <mutex>
+#include <utility>
 
 #include "wrls_internal.h"
 
@@ -698,93 +699,73 @@ hipError_t occupancy_batched_d(bool f16, int32_t block_threads, int *blocks_per_
         blocks_per_cu, reinterpret_cast<const void *>(&batch_kernel<D, float>), block_threads, 0);
 }
 
-// Entries K0 .. K0 + N - 1 of pixel jj of a state copy with NS entries per
-// pixel: the vector groups that hold them are read with 128-bit loads, the
-// scalar remainder with 32-bit ones.
-template <int NS, int K0, int N>
-__device__ __forceinline__ void load_entries(const float *state, Rsrc r_state, uint32_t jj,
-                                             float (&out)[N])
-{
-    constexpr int G = vec_planes(NS);
-    constexpr int GA = K0 / 4;
-    constexpr int GB = (K0 + N - 1) / 4 < G ? (K0 + N - 1) / 4 : G - 1;
-    if constexpr (K0 < 4 * G) {
-        f4_t v[GB - GA + 1];
-#pragma unroll
-        for (int q = 0; q <= GB - GA; q++) v[q] = *vec_at(state, vgroup(GA + q), vslot(jj, NS));
-#pragma unroll
-        for (int m = 0; m < N; m++)
-            if (K0 + m < 4 * G) out[m] = v[(K0 + m) / 4 - GA][(K0 + m) % 4];
-    }
-#pragma unroll
-    for (int m = 0; m < N; m++)
-        if (K0 + m >= 4 * G) out[m] = bload(r_state, sslot(jj, NS), sgroup(NS, K0 + m - 4 * G));
-}
-
 // Spatial blend of neighbour-model predictions (Sec. 5.3, last paragraph),
 // after a step, over the current state.  Pixel i's final colour averages the
 // predictions p_i beta_k^T of the models k in the 5x5 window centred on i
 // (pixels inside the image) with the bilateral weight
 //   w_ik = exp(-|x_k - x_i|^2 / (2 sigma_s^2) - |yhat_k - yhat_i|^2 / (2 sigma_r^2)),
 // yhat being the step's output.  Since every prediction uses p_i, the sum is
-// p_i (sum_k w_ik beta_k^T) / sum_k w_ik: per channel a weighted 5x5 stencil
-// over the D beta entries, then one dot product.
+// p_i (sum_k w_ik beta_k^T) / sum_k w_ik: a weighted 5x5 stencil over each of
+// the 3 d beta entries, then one dot product per channel.
 //
 // One workgroup per 64 x kBlendTH tile; each thread computes RPT vertically
 // adjacent pixels.  The guide of the tile and its 2-pixel halo is staged in
-// LDS and every thread keeps its 25 RPT weights in registers; then, one
-// channel at a time, the channel's beta entries of the halo are staged in
-// LDS and accumulated.  A thread reads each halo row once for all RPT of
-// its pixels (LDS traffic per pixel: 5 (RPT + 4) / RPT reads instead of 25).
-// LDS holds the entries in groups of four, one 16-byte vector per halo pixel
-// and group (the guide likewise, padded): a neighbour costs one 128-bit read
-// per group, every read is an immediate offset from one base address (no
-// per-read address arithmetic on the vector ALU, which bounds this kernel),
-// and a wave's read covers 1 KB of consecutive bytes (no bank conflicts).
-// Halo reads of neighbouring tiles hit L2; each state entry crosses HBM
-// about once.
+// LDS and every thread keeps its 25 RPT weights in registers.  Then the beta
+// entries of the halo go through LDS one state vector group (four entries)
+// at a time: while the workgroup accumulates group u from one of two LDS
+// slots, the loads of groups u + 1 .. u + kBlendAhead are in flight in
+// registers, and group u + 1 is written to the other slot after the
+// accumulation (a barrier per group).  Each group's four sums are folded into
+// their channels' dot products as soon as they are complete, so a thread
+// holds 4 RPT partial sums rather than a whole channel's.  Halo pixels
+// outside the image are never loaded: their staging registers stay zero.
+// A thread reads each halo row once for all RPT of its pixels (LDS reads per
+// pixel: 5 (RPT + 4) / RPT per group instead of 25); every read is an
+// immediate offset from one base address, and a wave's read covers 1 KB of
+// consecutive bytes.  Halo reads of neighbouring tiles hit L2; each state
+// entry crosses HBM about once.
 constexpr int kBlendRW = kBlendTW + 2 * kBlendR;
 constexpr int kBlendRH = kBlendTH + 2 * kBlendR;
 constexpr int kBlendRN = kBlendRW * kBlendRH;
 constexpr int kBlendThreads = kBlendTW * kBlendTH / kBlendRPT;
 constexpr int kBlendSlots = (kBlendRN + kBlendThreads - 1) / kBlendThreads;
 constexpr int kBlendK = 2 * kBlendR + 1;  // window side
-// Blend tiles run in vertical strips of this many tiles (0: the full image
-// width), so that a tile's top halo rows, which the tile above also read,
-// are still in L2.  Strips of 3 and 8 tiles cut 4K reads but timed the same
-// as the full width (4K d = 10: 421-425 us against 422), and 2% slower at
-// 1080p and in paper mode.
-constexpr int kBlendStripTiles = 0;
+// State groups whose loads are in flight in registers while a group is
+// accumulated.  Two hold 16 more registers across the accumulation, which
+// costs a wave per SIMD and measured slower (4K d = 10: 384 against 359 us).
+constexpr int kBlendAhead = 1;
 
-// The occupancy hint caps registers: left alone, the scheduler keeps most of
-// a channel's LDS reads in flight and needs 168+ VGPRs at d = 8.
+// Calls f(integral_constant<int, I>) for I = 0 .. N - 1, in order.
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_seq(F &&f, std::integer_sequence<int, I...>)
+{
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    static_for_seq(f, std::make_integer_sequence<int, N>{});
+}
+
+// Four waves per SIMD (four workgroups per compute unit, 39 KB of LDS
+// each); every d fits in 128 registers without spilling.
 template <int D, typename InT, bool PAPER>
 __global__ void __launch_bounds__(kBlendThreads)
-__attribute__((amdgpu_waves_per_eu(D <= 7 ? 4 : (D <= 9 ? 3 : 2))))
+__attribute__((amdgpu_waves_per_eu(4)))
 blend_kernel(const BlendArgs a)
 {
     constexpr int RPT = kBlendRPT;
     constexpr int NS = state_floats(D) + (PAPER ? 3 : 0);
-    constexpr int NG = (D + 3) / 4;  // groups of four beta entries
-    // The guide is read only while the weights are computed, before the
-    // channel loop.  With three groups of beta entries (d >= 9) it shares
-    // LDS with the beta staging, a barrier separating the two uses: a
-    // workgroup holds 39 KB instead of 52 KB, so four fit on a compute unit
-    // instead of three (4K d = 10: 466 -> 422 us).  With fewer groups the
-    // registers bound occupancy anyway and the extra barrier costs (paper
-    // mode 44.7 -> 47.7 us), so the guide has its own LDS.
-    constexpr bool kShareGuide = NG >= 3;
-    __shared__ float4 s_lds[(kShareGuide ? NG : NG + 1) * kBlendRN];
-    float4 *const s_guide = kShareGuide ? s_lds : s_lds + NG * kBlendRN;
+    constexpr int NB = 3 * D;         // beta entries, first in the state
+    constexpr int UG = (NB + 3) / 4;  // state vector groups that hold them
+    constexpr int AH = kBlendAhead < UG ? kBlendAhead : UG;
+    static_assert(beta_entry0(D) == 0 && UG <= vec_planes(NS), "beta fills the first vector groups");
+    __shared__ float4 s_ring[2 * kBlendRN];
+    __shared__ float4 s_guide[kBlendRN];
 
     const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
-    int txi, tyi;
-    if constexpr (kBlendStripTiles > 0) {
-        tile_coords(tile, a.tiles_x, a.tiles_y, min(kBlendStripTiles, a.tiles_x), txi, tyi);
-    } else {
-        tyi = tile / a.tiles_x;
-        txi = tile - tyi * a.tiles_x;
-    }
+    const int tyi = tile / a.tiles_x;
+    const int txi = tile - tyi * a.tiles_x;
     const int x0 = txi * kBlendTW, y0 = tyi * kBlendTH;
     const int tid = (int)threadIdx.x;
     const int lx = tid % kBlendTW, ly = (tid / kBlendTW) * RPT;  // first of the thread's rows
@@ -793,15 +774,11 @@ blend_kernel(const BlendArgs a)
     const uint32_t pitch = (uint32_t)a.pitch;
     const Rsrc r_state = array_rsrc(a.state, (uint32_t)NS * pitch * 4u);
     const Rsrc r_guide = array_rsrc(a.guide, 3u * n * 4u);
-    // entry k of pixel jj of the current state
-    auto state_entry = [&](int k, uint32_t jj) {
-        uint32_t voff, soff;
-        entry_offsets(NS, D, k, jj, voff, soff);
-        return bload(r_state, voff, soff);
-    };
 
-    // Halo slots of this thread: global pixel index, or -1 outside the image.
+    // Halo slots of this thread: global pixel index, or -1 outside the image,
+    // and the byte offset of the pixel's 16-byte slot in a state group.
     int hj[kBlendSlots];
+    uint32_t hs[kBlendSlots];
 #pragma unroll
     for (int r = 0; r < kBlendSlots; r++) {
         const int sl = tid + r * kBlendThreads;
@@ -809,7 +786,39 @@ blend_kernel(const BlendArgs a)
         const int gx = x0 - kBlendR + hx, gy = y0 - kBlendR + hy;
         const bool in = sl < kBlendRN && gx >= 0 && gx < a.W && gy >= 0 && gy < a.H;
         hj[r] = in ? gy * a.W + gx : -1;
+        hs[r] = vslot(in ? (uint32_t)hj[r] : 0u, NS);
     }
+
+    // State group U of the halo: loaded into nx[U % AH] (lanes outside the
+    // image keep their zeros), written to LDS slot U % 2.  The state pointer
+    // passes through an empty asm at each load batch: otherwise the compiler
+    // computes every group's addresses ahead of time and keeps them in
+    // registers.
+    f4_t nx[AH][kBlendSlots];
+#pragma unroll
+    for (int k = 0; k < AH; k++)
+#pragma unroll
+        for (int r = 0; r < kBlendSlots; r++) nx[k][r] = f4_t{0.0f, 0.0f, 0.0f, 0.0f};
+    auto issue = [&](auto uu) {
+        constexpr int U = decltype(uu)::value;
+        const float *st = a.state;
+        asm volatile("" : "+s"(st));
+#pragma unroll
+        for (int r = 0; r < kBlendSlots; r++)
+            if (hj[r] >= 0) nx[U % AH][r] = *vec_at(st, vgroup(U), hs[r]);
+    };
+    auto put = [&](auto uu) {
+        constexpr int U = decltype(uu)::value;
+#pragma unroll
+        for (int r = 0; r < kBlendSlots; r++) {
+            const int sl = tid + r * kBlendThreads;
+            if (sl < kBlendRN) {
+                const f4_t v = nx[U % AH][r];
+                s_ring[(U % 2) * kBlendRN + sl] = make_float4(v[0], v[1], v[2], v[3]);
+            }
+        }
+    };
+    static_for<AH>([&](auto uu) { issue(uu); });
 
     // No early exit for pixels outside the image: every thread stages the halo.
     bool mine[RPT];
@@ -820,6 +829,12 @@ blend_kernel(const BlendArgs a)
         mine[r] = x < a.W && y < a.H;
         jr[r] = mine[r] ? (uint32_t)y * (uint32_t)a.W + (uint32_t)x : 0u;
     }
+    // entry k of pixel jj of the current state
+    auto state_entry = [&](int k, uint32_t jj) {
+        uint32_t voff, soff;
+        entry_offsets(NS, D, k, jj, voff, soff);
+        return bload(r_state, voff, soff);
+    };
     // The pixels' predictors p_i, entries 1..D-1 (non-finite as 0, as in
     // the step; p_0 = 1).
     const Rsrc r_feats = array_rsrc(a.feats, (uint32_t)(D - 1) * n * (uint32_t)sizeof(InT));
@@ -910,126 +925,74 @@ blend_kernel(const BlendArgs a)
 #pragma unroll
     for (int r = 0; r < RPT; r++) inv_den[r] = 1.0f / den[r];
 
-    // The channels' beta entries of the halo are fetched into registers (nx)
-    // and written to LDS.  For D <= 4 the fetch is software-pipelined:
-    // channel c + 1's loads are issued before channel c is accumulated and
-    // written to LDS after it (1080p paper mode: 51.6 -> 46.4 us).  For
-    // larger D the registers this holds across the accumulation cost more
-    // than the overlap gains (d = 8 drops to 3 waves per SIMD), so a
-    // channel is fetched just before it is staged.  A channel is dispatched
-    // to a compile-time value so that every state offset is static.  The
-    // state pointer passes through an empty asm at each fetch: otherwise
-    // the compiler computes all three channels' addresses ahead of the loop
-    // (they do not depend on the loop variable) and keeps them in registers.
-    constexpr bool kPipelined = D <= 4;
-    float nx[kBlendSlots][4 * NG];
-    // loads halo slots R0 .. R1 - 1 of channel C into nx
-    auto fetch = [&](auto cc, auto r0, auto r1) {
-        constexpr int C = decltype(cc)::value;
-        const float *st = a.state;
-        asm volatile("" : "+s"(st));
-#pragma unroll
-        for (int r = decltype(r0)::value; r < decltype(r1)::value; r++) {
-#pragma unroll
-            for (int m = 0; m < 4 * NG; m++) nx[r][m] = 0.0f;
-            if (hj[r] >= 0) {
-                float e[D];
-                load_entries<NS, beta_entry0(D) + C * D, D>(st, r_state, (uint32_t)hj[r], e);
-#pragma unroll
-                for (int m = 0; m < D; m++) nx[r][m] = e[m];
-            }
-        }
-    };
-    auto fetch_channel = [&](int c, auto r0, auto r1) {
-        if (c == 0)
-            fetch(std::integral_constant<int, 0>{}, r0, r1);
-        else if (c == 1)
-            fetch(std::integral_constant<int, 1>{}, r0, r1);
-        else if (c == 2)
-            fetch(std::integral_constant<int, 2>{}, r0, r1);
-    };
-    // writes halo slots R0 .. R1 - 1 from nx to LDS
-    auto stage = [&](auto r0, auto r1) {
-#pragma unroll
-        for (int r = decltype(r0)::value; r < decltype(r1)::value; r++) {
-            const int sl = tid + r * kBlendThreads;
-            if (sl < kBlendRN)
-#pragma unroll
-                for (int gq = 0; gq < NG; gq++)
-                    s_lds[gq * kBlendRN + sl] = make_float4(nx[r][4 * gq], nx[r][4 * gq + 1], nx[r][4 * gq + 2],
-                                                 nx[r][4 * gq + 3]);
-        }
-    };
-    using AllSlots0 = std::integral_constant<int, 0>;
-    using AllSlots1 = std::integral_constant<int, kBlendSlots>;
-    if constexpr (kPipelined) fetch_channel(0, AllSlots0{}, AllSlots1{});
-    float outc[RPT][3];
-    // kept rolled: unrolled, the compiler hoists every channel's loads and
-    // LDS reads and runs out of registers
-#pragma unroll 1
-    for (int c = 0; c < 3; c++) {
-        // the previous channel's reads (the guide's, before channel 0) are done
-        if (c > 0 || kShareGuide) __syncthreads();
-        if constexpr (kPipelined) {
-            stage(AllSlots0{}, AllSlots1{});
-            fetch_channel(c + 1, AllSlots0{}, AllSlots1{});
-        } else {
-            // two halves of the slots: the scheduling barrier keeps the
-            // compiler from issuing every slot's loads (and holding their
-            // registers) together
-            using Half = std::integral_constant<int, (kBlendSlots + 1) / 2>;
-            auto fetch_and_stage = [&](auto cc) {
-                fetch(cc, AllSlots0{}, Half{});
-                stage(AllSlots0{}, Half{});
-                __builtin_amdgcn_sched_barrier(0);
-                fetch(cc, Half{}, AllSlots1{});
-                stage(Half{}, AllSlots1{});
-            };
-            if (c == 0)
-                fetch_and_stage(std::integral_constant<int, 0>{});
-            else if (c == 1)
-                fetch_and_stage(std::integral_constant<int, 1>{});
-            else
-                fetch_and_stage(std::integral_constant<int, 2>{});
-        }
-        __syncthreads();
-        float acc[RPT][4 * NG];
+    // The first group to LDS, the next loads out, then group by group.
+    put(std::integral_constant<int, 0>{});
+    if constexpr (AH < UG) issue(std::integral_constant<int, AH>{});
+    __syncthreads();
+    float y[RPT][3];
+    static_for<UG>([&](auto uu) {
+        constexpr int U = decltype(uu)::value;
+        const float4 *const slot = s_ring + (U % 2) * kBlendRN;
+        float acc[RPT][4];
 #pragma unroll
         for (int r = 0; r < RPT; r++)
 #pragma unroll
-            for (int m = 0; m < 4 * NG; m++) acc[r][m] = 0.0f;
+            for (int e = 0; e < 4; e++) acc[r][e] = 0.0f;
 #pragma unroll
-        for (int gq = 0; gq < NG; gq++)
+        for (int hr = 0; hr < RPT + 2 * kBlendR; hr++) {
 #pragma unroll
-            for (int hr = 0; hr < RPT + 2 * kBlendR; hr++)
+            for (int dx = -kBlendR; dx <= kBlendR; dx++) {
+                const float4 bv = slot[(ly + hr) * kBlendRW + lx + kBlendR + dx];
+                const float b4[4] = {bv.x, bv.y, bv.z, bv.w};
 #pragma unroll
-                for (int dx = -kBlendR; dx <= kBlendR; dx++) {
-                    const float4 bv = s_lds[gq * kBlendRN + (ly + hr) * kBlendRW + lx + kBlendR + dx];
-                    const float b4[4] = {bv.x, bv.y, bv.z, bv.w};
+                for (int r = 0; r < RPT; r++) {
+                    const int dy = hr - r - kBlendR;
+                    if (dy < -kBlendR || dy > kBlendR) continue;
+                    const float wk = w[r][(dy + kBlendR) * kBlendK + (dx + kBlendR)];
 #pragma unroll
-                    for (int r = 0; r < RPT; r++) {
-                        const int dy = hr - r - kBlendR;
-                        if (dy < -kBlendR || dy > kBlendR) continue;
-                        const float wk = w[r][(dy + kBlendR) * kBlendK + (dx + kBlendR)];
-#pragma unroll
-                        for (int e = 0; e < 4; e++)
-                            if (4 * gq + e < D) acc[r][4 * gq + e] = fmaf(wk, b4[e], acc[r][4 * gq + e]);
-                    }
+                    for (int e = 0; e < 4; e++)
+                        if (4 * U + e < NB) acc[r][e] = fmaf(wk, b4[e], acc[r][e]);
                 }
+            }
+            // the row's products are done here, before the next row's reads
 #pragma unroll
-        for (int r = 0; r < RPT; r++) {
-            float yv = acc[r][0];  // p_0 = 1
+            for (int r = 0; r < RPT; r++)
 #pragma unroll
-            for (int m = 1; m < D; m++) yv = fmaf(p[r][m], acc[r][m], yv);
-            outc[r][c] = yv * inv_den[r];
+                for (int e = 0; e < 4; e++)
+                    if (4 * U + e < NB) asm volatile("" : "+v"(acc[r][e]));
         }
-    }
+        // entry k = 4 U + e is coefficient m = k % D of channel k / D
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            constexpr int k0 = 4 * U;
+            if (k0 + e >= NB) continue;
+            const int c = (k0 + e) / D, m = (k0 + e) % D;
+#pragma unroll
+            for (int r = 0; r < RPT; r++) {
+                y[r][c] = m == 0 ? acc[r][e] : fmaf(p[r][m], acc[r][e], y[r][c]);
+                // the group's sums are complete here: otherwise the compiler
+                // defers the arithmetic past the next barrier and holds
+                // several groups' LDS reads at once
+                asm volatile("" : "+v"(y[r][c]));
+            }
+        }
+        if constexpr (U + 1 < UG) {
+            __builtin_amdgcn_sched_barrier(0);
+            put(std::integral_constant<int, U + 1>{});
+            if constexpr (U + 1 + AH < UG) issue(std::integral_constant<int, U + 1 + AH>{});
+            __syncthreads();
+        }
+    });
+    // Stores without a branch (a pixel outside the image gets an offset past
+    // the array, which the buffer drops): behind a branch, the compiler sinks
+    // the whole accumulation into it and holds every LDS read at once.
     const Rsrc r_out = array_rsrc(a.out, 3u * n * 4u);
 #pragma unroll
-    for (int r = 0; r < RPT; r++)
-        if (mine[r])
+    for (int r = 0; r < RPT; r++) {
+        const uint32_t vo = mine[r] ? jr[r] * 4u : 0x80000000u;
 #pragma unroll
-            for (int c = 0; c < 3; c++) bstore(r_out, jr[r] * 4u, (uint32_t)c * n * 4u, outc[r][c]);
+        for (int c = 0; c < 3; c++) bstore(r_out, vo, (uint32_t)c * n * 4u, y[r][c] * inv_den[r]);
+    }
 }
 
 // A part of a batched step's frame table, passed by value as a kernel
