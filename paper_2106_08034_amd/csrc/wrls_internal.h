@@ -138,6 +138,7 @@ struct BlendArgs {
     float inv2ss, inv2sr;   // 1/(2 sigma_s^2), 1/(2 sigma_r^2); 0 turns a factor off
     int32_t tiles_x;        // blend tiles per image row
     int32_t tiles_y;
+    int32_t strip_w;        // tiles per vertical strip of the tile order (launch_blend sets it)
 };
 // Blend tile: kBlendTW x kBlendTH output pixels per workgroup of
 // kBlendTW * kBlendTH / kBlendRPT threads (each thread computes kBlendRPT

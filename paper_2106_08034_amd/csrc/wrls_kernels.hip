@@ -722,8 +722,10 @@ hipError_t occupancy_batched_d(bool f16, int32_t block_threads, int *blocks_per_
 // A thread reads each halo row once for all RPT of its pixels (LDS reads per
 // pixel: 5 (RPT + 4) / RPT per group instead of 25); every read is an
 // immediate offset from one base address, and a wave's read covers 1 KB of
-// consecutive bytes.  Halo reads of neighbouring tiles hit L2; each state
-// entry crosses HBM about once.
+// consecutive bytes.  Halo reads of neighbouring tiles hit L2 (wide images
+// run in vertical strips of tiles, so that a tile row's bottom rows are
+// still there for the tile row below); each state entry crosses HBM about
+// once.
 constexpr int kBlendRW = kBlendTW + 2 * kBlendR;
 constexpr int kBlendRH = kBlendTH + 2 * kBlendR;
 constexpr int kBlendRN = kBlendRW * kBlendRH;
@@ -764,8 +766,8 @@ blend_kernel(const BlendArgs a)
     __shared__ float4 s_guide[kBlendRN];
 
     const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
-    const int tyi = tile / a.tiles_x;
-    const int txi = tile - tyi * a.tiles_x;
+    int txi, tyi;
+    tile_coords(tile, a.tiles_x, a.tiles_y, a.strip_w, txi, tyi);
     const int x0 = txi * kBlendTW, y0 = tyi * kBlendTH;
     const int tid = (int)threadIdx.x;
     const int lx = tid % kBlendTW, ly = (tid / kBlendTW) * RPT;  // first of the thread's rows
@@ -1224,9 +1226,27 @@ const void *batched_kernel_fn(int d, bool f16)
 #undef WRLS_BATCH_FN
 }
 
-hipError_t launch_blend(int d, bool f16, bool paper, const BlendArgs &a, hipStream_t st)
+// Tiles per vertical strip of the blend's tile order.  A tile row re-reads
+// the bottom two source rows of the tile row above; that reuse stays in the
+// XCD's 4 MiB L2 only while a tile row's bytes (state groups, predictor
+// source, guide, output) leave room for it.  Wider rows run in strips of
+// about 1.25 MiB per tile row (4K at d = 10: 15 tiles; HBM reads 1.05x the
+// algorithmic bytes instead of 1.46x); narrower rows run whole (1080p at
+// d = 8: 2.3 MB per tile row, where strips measured 2-3% slower).
+static int blend_strip_w(int d, bool f16, bool paper, int tiles_x)
+{
+    const int64_t px_bytes = 16 * ((3 * d + 3) / 4) + (paper ? 12 : (d - 1) * (f16 ? 2 : 4)) + 12 + 12;
+    const int64_t tile_bytes = (int64_t)kBlendTW * kBlendTH * px_bytes;
+    if ((int64_t)tiles_x * tile_bytes <= (int64_t)3 << 20) return tiles_x;
+    const int64_t w = ((int64_t)5 << 18) / tile_bytes;
+    return (int)(w < 1 ? 1 : (w > tiles_x ? tiles_x : w));
+}
+
+hipError_t launch_blend(int d, bool f16, bool paper, const BlendArgs &args, hipStream_t st)
 {
     if (paper && d != 4) return hipErrorInvalidValue;
+    BlendArgs a = args;
+    a.strip_w = blend_strip_w(d, f16, paper, a.tiles_x);
     switch (d) {
     case 1: return launch_blend_d<1>(f16, false, a, st);
     case 2: return launch_blend_d<2>(f16, false, a, st);
