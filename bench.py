@@ -103,6 +103,27 @@ def measure_copy_gbs(torch, wrls, nbytes: int, reps: int = 10) -> float:
     return gbs
 
 
+def measure_probe_gbs(torch, stream, frames, reps: int, nbytes: int) -> float:
+    """Read+write bandwidth of wrls_traffic_probe on the step's own stream and
+    frames: the step's loads and stores (same bytes per launch, same tile
+    order and access forms) without the reprojection and the arithmetic,
+    timed with HIP events on the current stream.  The stream's state is left
+    as it was."""
+    tmp = torch.empty((3, stream.H, stream.W), dtype=torch.float32, device="cuda")
+    for i in range(3):
+        stream.traffic_probe(*frames[i % len(frames)], out=tmp)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for i in range(reps):
+        stream.traffic_probe(*frames[i % len(frames)], out=tmp)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = nbytes * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del tmp
+    return gbs
+
+
 def kernel_source_hash() -> str:
     """Identifies the code that shapes a launch's memory traffic: the kernels,
     the internal header whose constants they compile with, and the host side
@@ -620,6 +641,11 @@ def bench_step(args, workload: str, with_cpu: bool, parity_frames=None, with_ble
                                        "gbs": round(copy_gbs, 1),
                                        "frac": round(achieved_gbs / copy_gbs, 4)}},
     }
+    probe_gbs = measure_probe_gbs(torch, stream, dev_frames, max(K, 10), bpp * npix)
+    res["roofline"]["measured_probe"] = {
+        "kernel": "wrls_traffic_probe: the step's loads and stores, same bytes per launch, "
+                  "without reprojection or arithmetic",
+        "gbs": round(probe_gbs, 1), "frac": round(achieved_gbs / probe_gbs, 4)}
 
     if with_blend:
         # the spatial blend (a second kernel after the step), timed on its

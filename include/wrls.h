@@ -328,6 +328,21 @@ wrls_status wrls_batch_step(wrls_batch *b, int32_t n, wrls_stream *const *stream
 wrls_status wrls_batch_step_noalloc(int32_t n, wrls_stream *const *streams, const wrls_frame *frames,
                                     int32_t tile_w_log2, int32_t block_threads, void *hip_stream);
 
+/* The loads and stores of one wrls_step of s without the reprojection and
+ * the arithmetic: a measurement reference for the step, which the benchmark
+ * reports beside the HBM peak and the plain copy.  Same arguments, checks
+ * and launch shape as wrls_step (Sec. 5.2-5.3 define what the step
+ * computes; this computes nothing of it).  Each pixel loads its motion,
+ * features, colour and variance, reads its own state entries from the
+ * current copy (no gather) and writes them unchanged to the stream's other
+ * copy, and writes out[c] = colour[c] (plus, in channel 0, the sum of the
+ * other inputs), so the values in out mean nothing.  The stream's current
+ * state and frame count are untouched: the next wrls_step proceeds as if
+ * the probe had not run.  Stream-ordered; returns without synchronising.
+ * WRLS_EINVAL on a bad argument. */
+wrls_status wrls_traffic_probe(wrls_stream *s, const void *color, const void *features,
+                               const float *variance, const float *motion, float *out);
+
 /* Device-to-device copy of `bytes` bytes, in the state kernels' access
  * form: 16-byte loads and non-temporal 16-byte stores, one vector per
  * thread.  A utility (for example to snapshot outputs), and the read+write

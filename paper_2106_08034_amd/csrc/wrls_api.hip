@@ -360,6 +360,20 @@ wrls_status wrls_step(wrls_stream *s, const void *color, const void *features,
     return WRLS_OK;
 }
 
+wrls_status wrls_traffic_probe(wrls_stream *s, const void *color, const void *features,
+                               const float *variance, const float *motion, float *out)
+{
+    if (!s) return fail(WRLS_EINVAL, "stream handle is NULL");
+    wrls::FrameArgs a;
+    wrls_status rc = frame_args(s, color, features, variance, motion, out, &a);
+    if (rc != WRLS_OK) return rc;
+    a.fresh = 0;  // the motion is read as in a step with history
+    hipError_t e = wrls::launch_probe(s->prm.d, s->prm.in_dtype == WRLS_F16,
+                                      s->prm.weight_mode == WRLS_W_PAPER, a, s->tile, s->st);
+    if (e != hipSuccess) return hip_fail(e, "probe launch");
+    return WRLS_OK;  // no advance: the current state copy is untouched
+}
+
 wrls_status wrls_blend(const wrls_stream *s, const void *features, const float *temporal,
                        float sigma_s, float sigma_r, float *out)
 {

@@ -157,6 +157,10 @@ hipError_t launch_reset(float *state, int64_t npix, int d, int S, float p0, hipS
 hipError_t launch_convert(float *state, float *planes, int64_t npix, int d, int S, int k0,
                           int count, bool to_state, hipStream_t st);
 hipError_t launch_step(int d, bool f16, const FrameArgs &a, TileShape ts, hipStream_t st);
+// The step's loads and stores without reprojection or arithmetic (a
+// measurement reference): a's state_in is moved unchanged to state_out.
+hipError_t launch_probe(int d, bool f16, bool paper, const FrameArgs &a, TileShape ts,
+                        hipStream_t st);
 // n16 16-byte vectors from src to dst (16-byte loads, non-temporal stores).
 hipError_t launch_copy(void *dst, const void *src, size_t n16, hipStream_t st);
 // The paper's own predictor and weight (d = 4, state with history).

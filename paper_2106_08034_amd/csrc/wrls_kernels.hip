@@ -592,6 +592,55 @@ __global__ void __launch_bounds__(256) reset_kernel(float *state, int64_t npix, 
     }
 }
 
+// A measurement reference for the step: its loads and stores in its tile
+// order and access forms, without the reprojection and the arithmetic.  Each
+// pixel loads what a step loads (motion, NF feature planes, colour, variance
+// when given), reads its own NS state entries from the previous copy (no
+// gather: one tap at the pixel itself), and stores them to the other copy
+// with an output.  The output is a plain sum of the loaded inputs, so that no
+// load is dead.  The state is moved unchanged.
+template <int NS, int NF, typename InT>
+__global__ void __launch_bounds__(256) probe_kernel(const FrameArgs a, const TileShape ts)
+{
+    constexpr int G = vec_planes(NS);
+    const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    int tx, ty;
+    tile_coords(tile, a.tiles_x, a.tiles_y, a.strip_w, tx, ty);
+    const int x = (tx << ts.tw_log2) + ((int)threadIdx.x & ((1 << ts.tw_log2) - 1));
+    const int y = ty * (ts.block_threads >> ts.tw_log2) + ((int)threadIdx.x >> ts.tw_log2);
+    if (x >= a.W || y >= a.H) return;
+    const uint32_t n = (uint32_t)a.W * (uint32_t)a.H;
+    const uint32_t j = (uint32_t)y * (uint32_t)a.W + (uint32_t)x;
+    const InT *tag = nullptr;
+    const uint32_t in_bytes = n * (uint32_t)sizeof(InT);
+    float vx, vy;
+    load_motion(a, j, n, vx, vy);
+    float sum = vx + vy;
+    if constexpr (NF > 0) {
+        const Rsrc r_feats = array_rsrc(a.feats, (uint32_t)NF * in_bytes);
+#pragma unroll
+        for (int i = 0; i < NF; i++) sum += load_in(r_feats, tag, n, i, j);
+    }
+    const Rsrc r_color = array_rsrc(a.color, 3u * in_bytes);
+    float out[3];
+#pragma unroll
+    for (int c = 0; c < 3; c++) out[c] = load_in(r_color, tag, n, c, j);
+    if (a.var) sum += bload(array_rsrc(a.var, n * 4u), j * 4u, 0u);
+    float st[NS];
+    const uint32_t vj = vslot(j, NS);
+#pragma unroll
+    for (int g = 0; g < G; g++) {
+        const f4_t v = *vec_at(a.state_in, vgroup(g), vj);
+#pragma unroll
+        for (int e = 0; e < 4; e++) st[4 * g + e] = v[e];
+    }
+    const Rsrc src = array_rsrc(a.state_in, (uint32_t)NS * (uint32_t)a.pitch * 4u);
+#pragma unroll
+    for (int k = 4 * G; k < NS; k++) st[k] = bload(src, sslot(j, NS), sgroup(NS, k - 4 * G));
+    out[0] += sum;
+    store_pixel<NS>(a, j, n, st, out);
+}
+
 // Plain copy of n16 16-byte vectors, one per thread: the 16-byte loads and
 // non-temporal 16-byte stores of the state accesses, without the gather.
 __global__ void __launch_bounds__(256) copy_kernel(const f4_t *src, f4_t *dst, size_t n16)
@@ -1167,6 +1216,44 @@ hipError_t launch_step_paper(bool f16, const FrameArgs &a, TileShape ts, hipStre
     else
         hipLaunchKernelGGL((paper_step_kernel<float>), grid, block, lds, st, b, ts);
     return hipGetLastError();
+}
+
+template <int NS, int NF>
+hipError_t launch_probe_ns(bool f16, const FrameArgs &a, TileShape ts, hipStream_t st)
+{
+    const int tw = 1 << ts.tw_log2;
+    const int th = ts.block_threads >> ts.tw_log2;
+    FrameArgs b = a;
+    b.tiles_x = (a.W + tw - 1) / tw;
+    b.tiles_y = (a.H + th - 1) / th;
+    const int strip_w = ts.strip_w <= 0 ? b.tiles_x : ts.strip_w;
+    b.strip_w = strip_w > b.tiles_x ? b.tiles_x : strip_w;
+    const dim3 grid((unsigned)(b.tiles_x * b.tiles_y)), block((unsigned)ts.block_threads);
+    (void)hipGetLastError();  // report this launch's error, not an older one
+    if (f16)
+        hipLaunchKernelGGL((probe_kernel<NS, NF, _Float16>), grid, block, 0, st, b, ts);
+    else
+        hipLaunchKernelGGL((probe_kernel<NS, NF, float>), grid, block, 0, st, b, ts);
+    return hipGetLastError();
+}
+
+hipError_t launch_probe(int d, bool f16, bool paper, const FrameArgs &a, TileShape ts,
+                        hipStream_t st)
+{
+    if (paper) return d == 4 ? launch_probe_ns<kPaperNS, 0>(f16, a, ts, st) : hipErrorInvalidValue;
+    switch (d) {
+    case 1: return launch_probe_ns<state_floats(1), 0>(f16, a, ts, st);
+    case 2: return launch_probe_ns<state_floats(2), 1>(f16, a, ts, st);
+    case 3: return launch_probe_ns<state_floats(3), 2>(f16, a, ts, st);
+    case 4: return launch_probe_ns<state_floats(4), 3>(f16, a, ts, st);
+    case 5: return launch_probe_ns<state_floats(5), 4>(f16, a, ts, st);
+    case 6: return launch_probe_ns<state_floats(6), 5>(f16, a, ts, st);
+    case 7: return launch_probe_ns<state_floats(7), 6>(f16, a, ts, st);
+    case 8: return launch_probe_ns<state_floats(8), 7>(f16, a, ts, st);
+    case 9: return launch_probe_ns<state_floats(9), 8>(f16, a, ts, st);
+    case 10: return launch_probe_ns<state_floats(10), 9>(f16, a, ts, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_step(int d, bool f16, const FrameArgs &a, TileShape ts, hipStream_t st)

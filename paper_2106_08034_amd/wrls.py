@@ -83,6 +83,7 @@ SIGNATURES = {
     "wrls_batch_step_noalloc": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(_VP),
                                                ctypes.POINTER(wrls_frame), ctypes.c_int32,
                                                ctypes.c_int32, _VP]),
+    "wrls_traffic_probe": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP]),
     "wrls_device_copy": (ctypes.c_int, [_VP, _VP, ctypes.c_size_t, _VP]),
     "wrls_last_error": (ctypes.c_char_p, []),
     "wrls_version": (ctypes.c_char_p, []),
@@ -193,6 +194,11 @@ def wrls_frames(h: int) -> int:
 def wrls_step(h: int, color, features, variance, motion, out):
     _check(lib().wrls_step(h, _ptr(color), _ptr(features), _ptr(variance), _ptr(motion),
                            _ptr(out)))
+
+
+def wrls_traffic_probe(h: int, color, features, variance, motion, out):
+    _check(lib().wrls_traffic_probe(h, _ptr(color), _ptr(features), _ptr(variance), _ptr(motion),
+                                    _ptr(out)))
 
 
 def wrls_get_state(h: int, P_packed, beta):
@@ -364,6 +370,24 @@ class Stream:
         self._chk(out, (3, H, W), torch.float32, "out")
         wrls_step(self.handle, color, features if (d > 1 and not self.paper) else None, variance,
                   motion, out)
+        return out
+
+    def traffic_probe(self, color, features, variance, motion=None, out=None):
+        """wrls_traffic_probe: the step's loads and stores without the
+        reprojection and the arithmetic (a measurement reference; the
+        stream's state is left as it was, and out holds no result)."""
+        torch = self._torch
+        W, H, d = self.W, self.H, self.d
+        self._chk(color, (3, H, W), self.in_dtype, "color")
+        if d > 1 and not self.paper:
+            self._chk(features, (d - 1, H, W), self.in_dtype, "features")
+        self._chk(variance, (H, W), torch.float32, "variance")
+        self._chk(motion, (2, H, W), torch.float32, "motion")
+        if out is None:
+            out = torch.empty((3, H, W), dtype=torch.float32, device=color.device)
+        self._chk(out, (3, H, W), torch.float32, "out")
+        wrls_traffic_probe(self.handle, color, features if (d > 1 and not self.paper) else None,
+                           variance, motion, out)
         return out
 
     def reset(self):

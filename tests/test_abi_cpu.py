@@ -146,6 +146,7 @@ def test_null_arguments():
     assert L.wrls_set_tile(None, 6, 256, 0) == wrls.WRLS_EINVAL
     assert L.wrls_get_tile(None, None, None, None) == wrls.WRLS_EINVAL
     assert L.wrls_blend(None, None, None, 1.0, 1.0, None) == wrls.WRLS_EINVAL
+    assert L.wrls_traffic_probe(None, None, None, None, None, None) == wrls.WRLS_EINVAL
     L.wrls_params_default(None, 1, 1, 1)  # ignored, must not crash
     with pytest.raises(wrls.WrlsError):
         wrls.wrls_reset(None)

@@ -85,6 +85,12 @@ def test_blend_c2_full_size_1080p():
     _run_then_blend(synth.c2(frames=4), 4, [(1.5, 0.15)])
 
 
+def test_blend_c3_full_size_4k():
+    # 4K at d = 10 is wide enough that the tiles run in vertical strips;
+    # every pixel, strip edges included, is compared.
+    _run_then_blend(synth.c3(frames=3), 3, [(1.5, 0.15)])
+
+
 @pytest.mark.parametrize("d", list(range(1, 11)))
 def test_blend_every_d(d):
     rng = np.random.default_rng(300 + d)

@@ -327,3 +327,46 @@ def test_device_copy_bitwise():
     with pytest.raises(wrls.WrlsError):
         wrls.wrls_device_copy(dst, src[1:5])  # misaligned source
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("case", ["c2_d8_f32", "c3_d10_f16", "paper_d4"])
+def test_traffic_probe_leaves_the_stream_alone(case):
+    """wrls_traffic_probe (the step's loads and stores without reprojection
+    or arithmetic, the benchmark's reference) run between two steps changes
+    nothing: the later steps' outputs and the final state are bitwise those
+    of a stream that never ran it.  Its output channels 1 and 2 are the
+    colour it read (widened to FP32)."""
+    import torch
+    from paper_2106_08034_amd import wrls
+    wl = synth.c3(width=203, height=77, frames=4) if case == "c3_d10_f16" else \
+        synth.c2(width=197, height=83, frames=4)
+    paper = case == "paper_d4"
+    d = 4 if paper else wl.d
+    mode = "paper" if paper else "invvar"
+    src = synth.FrameSource(wl)
+    frames = []
+    for _ in range(4):
+        f = src.next()
+        frames.append((to_dev(f.color), None if paper else to_dev(f.feats),
+                       None if paper else to_dev(f.var), to_dev(f.motion)))
+    log("case traffic probe %s" % case)
+    a = wrls.Stream(wl.width, wl.height, d, in_dtype=wl.in_dtype, weight_mode=mode)
+    b = wrls.Stream(wl.width, wl.height, d, in_dtype=wl.in_dtype, weight_mode=mode)
+    for t, f in enumerate(frames):
+        if t == 2:
+            po = a.traffic_probe(*f)
+            torch.cuda.synchronize()
+            assert torch.equal(po[1:], f[0][1:].float()), case
+            assert a.frames == 2, a.frames
+        oa, ob = a.step(*f), b.step(*f)
+        assert torch.equal(oa, ob), (case, t)
+    Pa, Ba = a.get_state()
+    Pb, Bb = b.get_state()
+    assert torch.equal(Pa, Pb) and torch.equal(Ba, Bb), case
+    if paper:
+        assert torch.equal(a.get_history(), b.get_history()), case
+    with pytest.raises(wrls.WrlsError):
+        wrls.wrls_traffic_probe(a.handle, None, frames[0][1], frames[0][2], frames[0][3], po)  # no colour
+    a.close()
+    b.close()
+    torch.cuda.synchronize()
