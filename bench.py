@@ -149,12 +149,19 @@ def load_traffic(workload: str, kernel: str = ""):
 
 
 def cpu_model() -> str:
-    """The host CPU's model name (lscpu), for the CPU baseline."""
+    """The host CPU's model name (lscpu), with its family, model and stepping
+    numbers (a virtual machine may report only a generic name), and the
+    host's logical CPU count, for the CPU baseline."""
     try:
         out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        f = {}
         for line in out.splitlines():
-            if line.startswith("Model name:"):
-                return line.split(":", 1)[1].strip()
+            if ":" in line:
+                k, v = line.split(":", 1)
+                f[k.strip()] = v.strip()
+        name = f.get("Model name", "unknown")
+        ids = ", ".join("%s %s" % (k.lower(), f[k]) for k in ("CPU family", "Model", "Stepping") if k in f)
+        return "%s (%s; %s logical CPUs)" % (name, ids, f.get("CPU(s)", "?"))
     except (OSError, subprocess.SubprocessError):
         pass
     return "unknown"

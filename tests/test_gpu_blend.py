@@ -91,6 +91,12 @@ def test_blend_c3_full_size_4k():
     _run_then_blend(synth.c3(frames=3), 3, [(1.5, 0.15)])
 
 
+def test_blend_wide_ragged_rows_in_strips():
+    # 3905 px at d = 10: 62 tiles per row (the last one 1 px wide), in strips
+    # of 15 tiles and a last strip of 2; two tile rows and a partial third.
+    _run_then_blend(synth.c3(width=3905, height=21, frames=3), 3, SIGMAS[:2])
+
+
 @pytest.mark.parametrize("d", list(range(1, 11)))
 def test_blend_every_d(d):
     rng = np.random.default_rng(300 + d)
