@@ -343,6 +343,24 @@ wrls_status wrls_batch_step_noalloc(int32_t n, wrls_stream *const *streams, cons
 wrls_status wrls_traffic_probe(wrls_stream *s, const void *color, const void *features,
                                const float *variance, const float *motion, float *out);
 
+/* Checked builds.  The library also builds as libwrls_checked.so, whose
+ * kernels test every reprojection tap, every 16-byte state access and every
+ * LDS index against its array before using it; a failing access is skipped
+ * and its site recorded.  wrls_checked_build returns 1 in such a build and
+ * 0 in the shipped one.  wrls_checked_failures synchronises the current
+ * device, stores in *site_flags (if not NULL) a bit mask of the sites that
+ * failed since the last call (bit 0: a gather tap, 1: a state or output
+ * store, 2: a blend halo load, 3: a blend LDS index, 4: a paper-mode LDS
+ * index, 5: a batched tile without a frame) and clears them; 0 means every
+ * access stayed inside its array.  WRLS_EUNSUPPORTED in the shipped build,
+ * WRLS_EHIP on a HIP failure.  wrls_checked_raise fails the checks of the
+ * sites in site_mask from a kernel enqueued on hip_stream (NULL: the null
+ * stream), so that a test can see the reporting path work end to end.  For
+ * tests and debugging, not for the hot path. */
+int32_t wrls_checked_build(void);
+wrls_status wrls_checked_failures(uint32_t *site_flags);
+wrls_status wrls_checked_raise(uint32_t site_mask, void *hip_stream);
+
 /* Device-to-device copy of `bytes` bytes, in the state kernels' access
  * form: 16-byte loads and non-temporal 16-byte stores, one vector per
  * thread.  A utility (for example to snapshot outputs), and the read+write

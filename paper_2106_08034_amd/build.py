@@ -11,6 +11,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libwrls.so")
+# the same sources with every kernel access tested (WRLS_CHECKED)
+LIB_CHECKED = os.path.join(HERE, "libwrls_checked.so")
 SOURCES = ["wrls_kernels.hip", "wrls_api.hip"]
 ARCH = os.environ.get("WRLS_OFFLOAD_ARCH", "gfx950")
 
@@ -27,19 +29,22 @@ def hipcc() -> str:
     return os.path.join(rocm, "bin", "hipcc")
 
 
-def build(verbose: bool = False) -> str:
-    """Compiles every source into libwrls.so; raises on failure."""
+def build(verbose: bool = False, checked: bool = False) -> str:
+    """Compiles every source into libwrls.so (checked: libwrls_checked.so,
+    with the kernels' access checks); raises on failure."""
+    out = LIB_CHECKED if checked else LIB
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc()] + HIPCC_FLAGS + ["-I", INCLUDE, "-I", CSRC, "-o", tmp] + srcs
+    tmp = out + ".tmp%d" % os.getpid()
+    cmd = [hipcc()] + HIPCC_FLAGS + (["-DWRLS_CHECKED"] if checked else []) + \
+        ["-I", INCLUDE, "-I", CSRC, "-o", tmp] + srcs
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed building libwrls.so")
-    os.replace(tmp, LIB)
-    return LIB
+        raise RuntimeError("hipcc failed building " + os.path.basename(out))
+    os.replace(tmp, out)
+    return out
 
 
 def needs_build() -> bool:
@@ -100,3 +105,4 @@ if __name__ == "__main__":
         print(resource_usage())
     else:
         print(build(verbose=True))
+        print(build(verbose=True, checked=True))

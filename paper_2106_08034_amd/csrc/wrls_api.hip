@@ -827,6 +827,35 @@ wrls_status wrls_device_copy(void *dst, const void *src, size_t bytes, void *hip
     return WRLS_OK;
 }
 
+wrls_status wrls_checked_failures(uint32_t *site_flags)
+{
+    uint32_t f[wrls::kNumCheckSites] = {};
+    hipError_t e = wrls::read_and_clear_checks(f);
+    if (e == hipErrorNotSupported) return fail(WRLS_EUNSUPPORTED, "this library was built without checks");
+    if (e != hipSuccess) return hip_fail(e, "reading the check flags");
+    uint32_t mask = 0;
+    for (int i = 0; i < wrls::kNumCheckSites; i++) mask |= f[i] ? 1u << i : 0u;
+    if (site_flags) *site_flags = mask;
+    return WRLS_OK;
+}
+
+wrls_status wrls_checked_raise(uint32_t site_mask, void *hip_stream)
+{
+    hipError_t e = wrls::raise_checks(site_mask, static_cast<hipStream_t>(hip_stream));
+    if (e == hipErrorNotSupported) return fail(WRLS_EUNSUPPORTED, "this library was built without checks");
+    if (e != hipSuccess) return hip_fail(e, "raising check flags");
+    return WRLS_OK;
+}
+
+int32_t wrls_checked_build(void)
+{
+#ifdef WRLS_CHECKED
+    return 1;
+#else
+    return 0;
+#endif
+}
+
 const char *wrls_last_error(void) { return g_err; }
 
 const char *wrls_version(void) { return "libwrls 0.1 gfx950"; }

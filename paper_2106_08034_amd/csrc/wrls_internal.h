@@ -148,6 +148,26 @@ constexpr int kBlendRPT = 2;
 constexpr int kBlendTH = 4 * kBlendRPT;
 constexpr int kBlendR = 2;
 
+// Checked builds (compiled with WRLS_CHECKED: libwrls_checked.so): the
+// kernels test every gathered tap, every 16-byte state access and every LDS
+// index against its array before use, skip a failing access and record its
+// site.  Sites, one flag each:
+enum CheckSite {
+    kChkGatherTap = 0,  // a reprojection tap outside the image or the state copy
+    kChkStateStore,     // a pixel's state or output store outside its arrays
+    kChkBlendHalo,      // a blend halo load outside the state copy
+    kChkBlendLds,       // a blend LDS index outside the staged tile
+    kChkPaperLds,       // a paper-mode 3x3 LDS index outside the staged tile
+    kChkBatchFrame,     // a batched tile mapped to no frame of the table
+    kNumCheckSites
+};
+// Copies the per-site flags of this device into flags[kNumCheckSites] and
+// clears them (synchronises the device).  hipErrorNotSupported in builds
+// without checks.
+hipError_t read_and_clear_checks(uint32_t *flags);
+// Raises the flags of the sites in mask from a kernel (checked builds).
+hipError_t raise_checks(uint32_t mask, hipStream_t st);
+
 // S: state entries per pixel (state_floats(d), plus 3 history entries in
 // paper mode).
 hipError_t launch_reset(float *state, int64_t npix, int d, int S, float p0, hipStream_t st);

@@ -30,6 +30,21 @@ constexpr int kNumXcd = 8;
 // written lines do not displace the gathered previous-frame state in L2.
 constexpr int kStorePolicy = 2;
 
+// Checks of the checked build (WRLS_CHECKED): expect(ok, site) is ok, and a
+// false ok also raises the site's flag (a plain store of 1 from each failing
+// lane).  In the shipped build it is the constant true, so the guarded
+// accesses compile exactly as without it.
+#ifdef WRLS_CHECKED
+__device__ uint32_t g_check_flags[kNumCheckSites];
+__device__ __forceinline__ bool expect(bool ok, int site)
+{
+    if (!ok) *(volatile uint32_t *)&g_check_flags[site] = 1u;
+    return ok;
+}
+#else
+__device__ __forceinline__ constexpr bool expect(bool, int) { return true; }
+#endif
+
 // Workgroups are dispatched to the XCDs round-robin (block b runs on XCD
 // b % 8).  Map block b to a tile index so that each XCD processes one
 // contiguous range of tiles: bijective on [0, nblocks).
@@ -88,6 +103,18 @@ __device__ __forceinline__ gcf4_t *vec_at(const float *state, uint32_t goff, uin
 __device__ __forceinline__ gf4_t *vec_at(float *state, uint32_t goff, uint32_t slot)
 {
     return (gf4_t *)(((gchar_t *)state + goff) + slot);
+}
+
+// Byte offset just past pixel i's entries in a state copy of NS entries
+// (the scalar remainder follows the vector groups in a chunk).
+template <int NS>
+__device__ __forceinline__ uint32_t pixel_end(uint32_t i)
+{
+    constexpr int G = vec_planes(NS);
+    if constexpr (NS % 4 != 0)
+        return sslot(i, NS) + sgroup(NS, NS - 4 * G - 1) + 4u;
+    else
+        return vslot(i, NS) + vgroup(G - 1) + 16u;
 }
 
 // Element j of plane `plane` of an input array of planes of n values.
@@ -152,6 +179,8 @@ __device__ __forceinline__ bool gather_state(const FrameArgs &a, int x, int y, f
         const int xn = min(x0 + (fx >= 0.5f ? 1 : 0), a.W - 1);
         const int yn = min(y0 + (fy >= 0.5f ? 1 : 0), a.H - 1);
         const uint32_t i = (uint32_t)yn * (uint32_t)a.W + (uint32_t)xn;
+        if (!expect(xn >= 0 && yn >= 0 && pixel_end<NS>(i) <= (uint32_t)NS * pitch * 4u, kChkGatherTap))
+            return false;
         const uint32_t vi = vslot(i, NS);
 #pragma unroll
         for (int g = 0; g < G; g++) {
@@ -167,6 +196,10 @@ __device__ __forceinline__ bool gather_state(const FrameArgs &a, int x, int y, f
     const uint32_t W = (uint32_t)a.W;
     const uint32_t i00 = (uint32_t)y0 * W + (uint32_t)x0, i10 = (uint32_t)y0 * W + (uint32_t)x1;
     const uint32_t i01 = (uint32_t)y1 * W + (uint32_t)x0, i11 = (uint32_t)y1 * W + (uint32_t)x1;
+    if (!expect(x0 >= 0 && y0 >= 0 && x0 <= x1 && y0 <= y1 && x1 < a.W && y1 < a.H &&
+                    pixel_end<NS>(i11) <= (uint32_t)NS * pitch * 4u,
+                kChkGatherTap))
+        return false;
     // Bilinear in nested-lerp form (exact for a constant field).  The taps
     // are issued GB vector groups at a time (4 GB 16-byte loads back to
     // back, behind a scheduling barrier, before any is consumed): one group
@@ -338,6 +371,7 @@ __device__ __forceinline__ void store_pixel(const FrameArgs &a, uint32_t j, uint
     const uint32_t pitch = (uint32_t)a.pitch;
     const Rsrc dst = array_rsrc(a.state_out, (uint32_t)NS * pitch * 4u);
     const Rsrc r_out = array_rsrc(a.out, 3u * n * 4u);
+    if (!expect(j < n && pixel_end<NS>(j) <= (uint32_t)NS * pitch * 4u, kChkStateStore)) return;
     const uint32_t vj = vslot(j, NS);
 #pragma unroll
     for (int g = 0; g < G; g++) {
@@ -420,6 +454,7 @@ __device__ __forceinline__ void update_pixel_paper(const FrameArgs &a, int x, in
     constexpr int NS = kPaperNS;
     const uint32_t n = (uint32_t)a.W * (uint32_t)a.H;
     const uint32_t j = (uint32_t)y * (uint32_t)a.W + (uint32_t)x;
+    (void)expect(c0 - rw - 1 >= 0 && c0 + rw + 1 < nc, kChkPaperLds);
     float yc[3];
 #pragma unroll
     for (int c = 0; c < 3; c++) yc[c] = col[c * nc + c0];
@@ -627,6 +662,7 @@ __global__ void __launch_bounds__(256) probe_kernel(const FrameArgs a, const Til
     for (int c = 0; c < 3; c++) out[c] = load_in(r_color, tag, n, c, j);
     if (a.var) sum += bload(array_rsrc(a.var, n * 4u), j * 4u, 0u);
     float st[NS];
+    if (!expect(pixel_end<NS>(j) <= (uint32_t)NS * (uint32_t)a.pitch * 4u, kChkGatherTap)) return;
     const uint32_t vj = vslot(j, NS);
 #pragma unroll
     for (int g = 0; g < G; g++) {
@@ -727,7 +763,7 @@ batch_kernel(const BatchTable *__restrict__ tab)
     const int n = tab->n;
     for (int k = 1; k <= kMaxBatch; k++) f += (k <= n && tab->prefix[k] <= t0 + r) ? 1 : 0;
     for (int t = t0 + r; t < t1; t += on_xcd) {
-        while (t >= tab->prefix[f + 1]) f++;
+        while (expect(f < n, kChkBatchFrame) && t >= tab->prefix[f + 1]) f++;
         const FrameArgs a = tab->frame[f];
         const int local = t - tab->prefix[f];
         const int ty = local / a.tiles_x;
@@ -836,9 +872,13 @@ blend_kernel(const BlendArgs a)
         const int hy = sl / kBlendRW, hx = sl - hy * kBlendRW;
         const int gx = x0 - kBlendR + hx, gy = y0 - kBlendR + hy;
         const bool in = sl < kBlendRN && gx >= 0 && gx < a.W && gy >= 0 && gy < a.H;
-        hj[r] = in ? gy * a.W + gx : -1;
-        hs[r] = vslot(in ? (uint32_t)hj[r] : 0u, NS);
+        hj[r] = in && expect(pixel_end<NS>((uint32_t)(gy * a.W + gx)) <= (uint32_t)NS * pitch * 4u,
+                             kChkBlendHalo)
+                    ? gy * a.W + gx
+                    : -1;
+        hs[r] = vslot(hj[r] >= 0 ? (uint32_t)hj[r] : 0u, NS);
     }
+    (void)expect(ly + RPT + 2 * kBlendR <= kBlendRH && lx + 2 * kBlendR < kBlendRW, kChkBlendLds);
 
     // State group U of the halo: loaded into nx[U % AH] (lanes outside the
     // image keep their zeros), written to LDS slot U % 2.  The state pointer
@@ -1123,6 +1163,44 @@ constexpr int kMaxDevices = 64;
 std::mutex g_scratch_mu;
 BatchTable *g_scratch_ptr[kMaxDevices];
 }  // namespace
+
+#ifdef WRLS_CHECKED
+// Fails the checks of the sites in mask (lane k for site k), to exercise
+// the reporting path from a kernel's flag store to the host's read.
+__global__ void raise_checks_kernel(uint32_t mask)
+{
+    const int k = (int)threadIdx.x;
+    if (k < kNumCheckSites) (void)expect(((mask >> k) & 1u) == 0u, k);
+}
+#endif
+
+hipError_t raise_checks(uint32_t mask, hipStream_t st)
+{
+#ifdef WRLS_CHECKED
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(raise_checks_kernel, dim3(1), dim3(64), 0, st, mask);
+    return hipGetLastError();
+#else
+    (void)mask;
+    (void)st;
+    return hipErrorNotSupported;
+#endif
+}
+
+hipError_t read_and_clear_checks(uint32_t *flags)
+{
+#ifdef WRLS_CHECKED
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return e;
+    e = hipMemcpyFromSymbol(flags, HIP_SYMBOL(g_check_flags), sizeof(g_check_flags));
+    if (e != hipSuccess) return e;
+    const uint32_t zero[kNumCheckSites] = {};
+    return hipMemcpyToSymbol(HIP_SYMBOL(g_check_flags), zero, sizeof(zero));
+#else
+    (void)flags;
+    return hipErrorNotSupported;
+#endif
+}
 
 hipError_t noalloc_table(BatchTable **tab)
 {

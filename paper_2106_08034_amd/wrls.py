@@ -84,6 +84,9 @@ SIGNATURES = {
                                                ctypes.POINTER(wrls_frame), ctypes.c_int32,
                                                ctypes.c_int32, _VP]),
     "wrls_traffic_probe": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP]),
+    "wrls_checked_build": (ctypes.c_int32, []),
+    "wrls_checked_failures": (ctypes.c_int, [ctypes.POINTER(ctypes.c_uint32)]),
+    "wrls_checked_raise": (ctypes.c_int, [ctypes.c_uint32, _VP]),
     "wrls_device_copy": (ctypes.c_int, [_VP, _VP, ctypes.c_size_t, _VP]),
     "wrls_last_error": (ctypes.c_char_p, []),
     "wrls_version": (ctypes.c_char_p, []),
@@ -199,6 +202,30 @@ def wrls_step(h: int, color, features, variance, motion, out):
 def wrls_traffic_probe(h: int, color, features, variance, motion, out):
     _check(lib().wrls_traffic_probe(h, _ptr(color), _ptr(features), _ptr(variance), _ptr(motion),
                                     _ptr(out)))
+
+
+CHECK_SITES = ("gather tap", "state or output store", "blend halo load", "blend LDS index",
+               "paper-mode LDS index", "batched tile without a frame")
+
+
+def wrls_checked_build() -> int:
+    """1 if the loaded library is the checked build, 0 if the shipped one."""
+    return int(lib().wrls_checked_build())
+
+
+def wrls_checked_raise(site_mask: int, hip_stream: Optional[int] = None):
+    """Checked builds: fails the checks of the sites in site_mask from a
+    kernel (to exercise the reporting path)."""
+    st = _current_hip_stream() if hip_stream is None else hip_stream
+    _check(lib().wrls_checked_raise(site_mask, st))
+
+
+def wrls_checked_failures() -> int:
+    """Checked builds: the bit mask of the sites whose access checks failed
+    since the last call (and clears them); 0 = every access in bounds."""
+    m = ctypes.c_uint32(0)
+    _check(lib().wrls_checked_failures(ctypes.byref(m)))
+    return m.value
 
 
 def wrls_get_state(h: int, P_packed, beta):

@@ -189,6 +189,24 @@ def test_batch_and_stream_in_reject_bad_arguments_without_gpu():
     assert "needs" in wrls.wrls_last_error()
 
 
+def test_checked_library_exports_the_same_abi():
+    """libwrls_checked.so (the kernels' access checks compiled in) exports
+    every symbol of the header and says it is the checked build; the
+    shipped library says it is not and has no check flags to read."""
+    import os
+    C = ctypes.CDLL(os.path.join(os.path.dirname(wrls.LIB_PATH), "libwrls_checked.so"))
+    for n in sorted(_declared()):
+        assert hasattr(C, n), "libwrls_checked.so does not export %s" % n
+    C.wrls_checked_build.restype = ctypes.c_int32
+    assert C.wrls_checked_build() == 1
+    assert wrls.wrls_checked_build() == 0
+    m = ctypes.c_uint32(7)
+    assert wrls.lib().wrls_checked_failures(ctypes.byref(m)) == wrls.WRLS_EUNSUPPORTED
+    assert m.value == 7
+    assert "without checks" in wrls.wrls_last_error()
+    assert wrls.lib().wrls_checked_raise(1, None) == wrls.WRLS_EUNSUPPORTED
+
+
 def test_device_copy_rejects_bad_arguments_on_the_host():
     """wrls_device_copy validates before any HIP call: null pointers,
     misalignment, a size that is not a multiple of 16 and overlap are
