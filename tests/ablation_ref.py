@@ -75,3 +75,20 @@ def run_forgetting(scene: str, width: int, height: int, frames: int, warm: int, 
         res[name] = {"psnr_db": psnr(float(np.mean(se[warm:]))),
                      "psnr_after_edit_db": psnr(float(np.mean(se[edit:])))}
     return res
+
+
+def per_frame_psnr(scene: str, width: int, height: int, frames: int):
+    """PSNR against the clean field of every frame of weighted RLS with
+    supplied features and fixed lambda = 0.98 (no reset at any frame), and of
+    the noisy input, on the c3 scene (colour LUT edit at frame 15, light
+    change at 22) or the c2 scene."""
+    wl = (synth.c3 if scene == "c3" else synth.c2)(width=width, height=height, frames=frames)
+    src = synth.FrameSource(wl)
+    o = oracle.Oracle(width, height, wl.d, lam=0.98, delta=math.exp(-synth.VAR_MU))
+    out, inp = [], []
+    for _ in range(frames):
+        f = src.next()
+        y = o.step(f.color, f.feats, f.var, f.motion)
+        out.append(psnr(float(np.mean((y - f.clean) ** 2))))
+        inp.append(psnr(float(np.mean((f.color.astype(np.float64) - f.clean) ** 2))))
+    return out, inp

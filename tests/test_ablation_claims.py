@@ -30,3 +30,16 @@ def test_automatic_forgetting_recovers_from_appearance_edits():
     assert c3["auto"]["psnr_db"] > c3["fixed"]["psnr_db"] + 0.2, c3
     c2 = ablation_ref.run_forgetting("c2", 192, 108, 30, 5, 15)
     assert c2["auto"]["psnr_db"] > c2["fixed"]["psnr_db"] - 0.15, c2
+
+
+def test_models_adapt_to_an_appearance_edit_without_a_reset():
+    """The models follow an abrupt change instead of being reset (Sec. 5.3):
+    at the c3 scene's colour LUT edit (frame 15) the fixed-lambda output
+    drops (25.1 -> 14.0 dB at 192x108, measured) but stays above the noisy
+    input (10.9 dB), then recovers frame after frame through the light
+    change at frame 22 (20.9 dB at frame 29)."""
+    out, inp = ablation_ref.per_frame_psnr("c3", 192, 108, 30)
+    assert out[15] < out[14] - 6.0, out
+    assert min(out[15:]) > max(inp[15:]) + 2.0, (out, inp)
+    assert all(b > a - 0.2 for a, b in zip(out[15:], out[16:])), out
+    assert out[29] > out[15] + 5.0, out
