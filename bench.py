@@ -124,6 +124,50 @@ def measure_probe_gbs(torch, stream, frames, reps: int, nbytes: int) -> float:
     return gbs
 
 
+def bench_paper_context(args) -> dict:
+    """A point shaped like the paper's own timing (Sec. 7.5: the whole
+    denoiser -- temporal feature, wRLS with p = [1, z], d = 4, and the 5x5
+    blend -- at 1280x720, about 12 ms per frame on a laptop GTX 1070): the
+    paper-mode step and the blend per frame at 1280x720, timed over a
+    sequence on one HIP stream.  Context only (other hardware, other year,
+    synthetic frames), not a target."""
+    import torch
+    import synth
+    from paper_2106_08034_amd import wrls
+    wl = synth.c2(width=1280, height=720, frames=8)
+    src = synth.FrameSource(wl)
+    frames = []
+    for _ in range(wl.frames):
+        f = src.next()
+        frames.append((torch.from_numpy(f.color).cuda(), torch.from_numpy(f.motion).cuda()))
+    s = wrls.Stream(wl.width, wl.height, 4, lam=0.98, weight_mode="paper")
+    out = torch.empty((3, wl.height, wl.width), device="cuda")
+    fin = torch.empty_like(out)
+    ss, sr = args.blend_sigmas
+    for t in range(3):
+        s.step(frames[t][0], None, None, frames[t][1], out=out)
+        s.blend(None, out, ss, sr, out=fin)
+    K = 30
+    cs = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(cs)
+    for t in range(K):
+        c, m = frames[(3 + t) % wl.frames]
+        s.step(c, None, None, m, out=out)
+        s.blend(None, out, ss, sr, out=fin)
+    e1.record(cs)
+    torch.cuda.synchronize()
+    s.close()
+    ms = e0.elapsed_time(e1) / K
+    return {"workload": "1280x720, paper mode (d = 4, temporal feature, Eq. 13 weight) + 5x5 blend, "
+                        "step and blend per frame",
+            "ms_per_frame": round(ms, 4),
+            "paper": {"ms_per_frame": 12.0, "plus_minus_ms": 2.5,
+                      "hardware": "Nvidia GTX 1070 (laptop), whole denoiser, Sec. 7.5"},
+            "note": "context only: different hardware, year and inputs; not a target"}
+
+
 def kernel_source_hash() -> str:
     """Identifies the code that shapes a launch's memory traffic: the kernels,
     the internal header whose constants they compile with, and the host side
@@ -905,6 +949,7 @@ def main():
         line["c4_batched"] = bench_batched(args, tune=args.tune)
         torch.cuda.empty_cache()
         line["serving"] = bench_serving(args)
+        line["paper_context"] = bench_paper_context(args)
     print(json.dumps(line), flush=True)
 
 
