@@ -797,13 +797,14 @@ hipError_t occupancy_batched_d(bool f16, int32_t block_threads, int *blocks_per_
 // adjacent pixels.  The guide of the tile and its 2-pixel halo is staged in
 // LDS and every thread keeps its 25 RPT weights in registers.  Then the beta
 // entries of the halo go through LDS one state vector group (four entries)
-// at a time: while the workgroup accumulates group u from one of two LDS
-// slots, the loads of groups u + 1 .. u + kBlendAhead are in flight in
-// registers, and group u + 1 is written to the other slot after the
-// accumulation (a barrier per group).  Each group's four sums are folded into
-// their channels' dot products as soon as they are complete, so a thread
-// holds 4 RPT partial sums rather than a whole channel's.  Halo pixels
-// outside the image are never loaded: their staging registers stay zero.
+// at a time, in two LDS slots filled by LDS-DMA loads (no staging
+// registers, no LDS stores): while the workgroup accumulates group u from
+// one slot, the loads of group u + 1 fill the other, and one barrier per
+// group hands it over.  The guide occupies the second slot until the weights
+// are computed.  Each group's four sums are folded into their channels' dot
+// products as soon as they are complete, so a thread holds 4 RPT partial
+// sums rather than a whole channel's.  Halo pixels outside the image are
+// never loaded: their LDS entries are zeroed once.
 // A thread reads each halo row once for all RPT of its pixels (LDS reads per
 // pixel: 5 (RPT + 4) / RPT per group instead of 25); every read is an
 // immediate offset from one base address, and a wave's read covers 1 KB of
@@ -817,10 +818,6 @@ constexpr int kBlendRN = kBlendRW * kBlendRH;
 constexpr int kBlendThreads = kBlendTW * kBlendTH / kBlendRPT;
 constexpr int kBlendSlots = (kBlendRN + kBlendThreads - 1) / kBlendThreads;
 constexpr int kBlendK = 2 * kBlendR + 1;  // window side
-// State groups whose loads are in flight in registers while a group is
-// accumulated.  Two hold 16 more registers across the accumulation, which
-// costs a wave per SIMD and measured slower (4K d = 10: 384 against 359 us).
-constexpr int kBlendAhead = 1;
 
 // Calls f(integral_constant<int, I>) for I = 0 .. N - 1, in order.
 template <typename F, int... I>
@@ -834,21 +831,48 @@ __device__ __forceinline__ void static_for(F &&f)
     static_for_seq(f, std::make_integer_sequence<int, N>{});
 }
 
-// Four waves per SIMD (four workgroups per compute unit, 39 KB of LDS
-// each); every d fits in 128 registers without spilling.
+// 16 bytes per lane from a buffer straight into LDS (buffer_load_dwordx4
+// with the lds bit): lane l of the wave writes LDS bytes lds + 16 l ..
+// lds + 16 l + 15, M0 holding the wave's LDS base; lanes outside the exec
+// mask write nothing.  Inline assembly, because the compiler makes every
+// LDS read after such a load wait for all of them to land, a wait the blend
+// places itself (wait_vm).  The asm has no register output, and M0 is used
+// by nothing else in the kernels (the compiler notes that it does not
+// preserve a reserved register named as clobbered; nothing here needs it
+// to).
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Winline-asm"
+__device__ __forceinline__ void lds_dma16(Rsrc r, uint32_t lds, uint32_t voff, uint32_t soff)
+{
+    asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tbuffer_load_dwordx4 %1, %2, %3 offen lds"
+                 :
+                 : "s"(lds), "v"(voff), "s"(r), "s"(soff)
+                 : "memory", "m0");
+}
+#pragma clang diagnostic pop
+// Wait until no vector memory operation of this wave is in flight.
+__device__ __forceinline__ void wait_vm0()
+{
+    __builtin_amdgcn_s_waitcnt((7 << 4) | (15 << 8));  // vmcnt(0); expcnt, lgkmcnt not waited on
+}
+
+// 26 KB of LDS per workgroup.  Five waves per SIMD (five workgroups per
+// compute unit) where the registers fit in 96 without spilling (d <= 5,
+// paper mode), else four (every d fits in 128).
 template <int D, typename InT, bool PAPER>
 __global__ void __launch_bounds__(kBlendThreads)
-__attribute__((amdgpu_waves_per_eu(4)))
+__attribute__((amdgpu_waves_per_eu(D <= 5 ? 5 : 4)))
 blend_kernel(const BlendArgs a)
 {
     constexpr int RPT = kBlendRPT;
     constexpr int NS = state_floats(D) + (PAPER ? 3 : 0);
     constexpr int NB = 3 * D;         // beta entries, first in the state
     constexpr int UG = (NB + 3) / 4;  // state vector groups that hold them
-    constexpr int AH = kBlendAhead < UG ? kBlendAhead : UG;
     static_assert(beta_entry0(D) == 0 && UG <= vec_planes(NS), "beta fills the first vector groups");
+    // Two LDS slots of one state group each; the second holds the guide
+    // until the weights are computed.
     __shared__ float4 s_ring[2 * kBlendRN];
-    __shared__ float4 s_guide[kBlendRN];
+    float4 *const s_guide = s_ring + kBlendRN;
 
     const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
     int txi, tyi;
@@ -864,6 +888,9 @@ blend_kernel(const BlendArgs a)
 
     // Halo slots of this thread: global pixel index, or -1 outside the image,
     // and the byte offset of the pixel's 16-byte slot in a state group.
+    // Slot r of the workgroup's threads is a run of kBlendThreads consecutive
+    // halo pixels, so a wave's slot r is 64 consecutive LDS entries: the
+    // layout an LDS-DMA load writes.
     int hj[kBlendSlots];
     uint32_t hs[kBlendSlots];
 #pragma unroll
@@ -878,38 +905,29 @@ blend_kernel(const BlendArgs a)
                     : -1;
         hs[r] = vslot(hj[r] >= 0 ? (uint32_t)hj[r] : 0u, NS);
     }
+    // LDS byte address of this wave's first halo slot in ring slot 0.
+    const uint32_t lds_wave =
+        (uint32_t)(uintptr_t)(__attribute__((address_space(3))) float4 *)s_ring +
+        (uint32_t)__builtin_amdgcn_readfirstlane(tid >> 6) * 64u * 16u;
     (void)expect(ly + RPT + 2 * kBlendR <= kBlendRH && lx + 2 * kBlendR < kBlendRW, kChkBlendLds);
 
-    // State group U of the halo: loaded into nx[U % AH] (lanes outside the
-    // image keep their zeros), written to LDS slot U % 2.  The state pointer
-    // passes through an empty asm at each load batch: otherwise the compiler
-    // computes every group's addresses ahead of time and keeps them in
-    // registers.
-    f4_t nx[AH][kBlendSlots];
-#pragma unroll
-    for (int k = 0; k < AH; k++)
-#pragma unroll
-        for (int r = 0; r < kBlendSlots; r++) nx[k][r] = f4_t{0.0f, 0.0f, 0.0f, 0.0f};
+    // State group U of the halo goes straight into ring slot U % 2.  Halo
+    // pixels outside the image keep zeros: zeroed once here in slot 0, and in
+    // slot 1 by the guide's staging.
     auto issue = [&](auto uu) {
         constexpr int U = decltype(uu)::value;
-        const float *st = a.state;
-        asm volatile("" : "+s"(st));
 #pragma unroll
         for (int r = 0; r < kBlendSlots; r++)
-            if (hj[r] >= 0) nx[U % AH][r] = *vec_at(st, vgroup(U), hs[r]);
+            if (hj[r] >= 0)
+                lds_dma16(r_state, lds_wave + (uint32_t)((U % 2) * kBlendRN + r * kBlendThreads) * 16u,
+                          hs[r], vgroup(U));
     };
-    auto put = [&](auto uu) {
-        constexpr int U = decltype(uu)::value;
 #pragma unroll
-        for (int r = 0; r < kBlendSlots; r++) {
-            const int sl = tid + r * kBlendThreads;
-            if (sl < kBlendRN) {
-                const f4_t v = nx[U % AH][r];
-                s_ring[(U % 2) * kBlendRN + sl] = make_float4(v[0], v[1], v[2], v[3]);
-            }
-        }
-    };
-    static_for<AH>([&](auto uu) { issue(uu); });
+    for (int r = 0; r < kBlendSlots; r++) {
+        const int sl = tid + r * kBlendThreads;
+        if (sl < kBlendRN && hj[r] < 0) s_ring[sl] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+    issue(std::integral_constant<int, 0>{});
 
     // No early exit for pixels outside the image: every thread stages the halo.
     bool mine[RPT];
@@ -1016,13 +1034,18 @@ blend_kernel(const BlendArgs a)
 #pragma unroll
     for (int r = 0; r < RPT; r++) inv_den[r] = 1.0f / den[r];
 
-    // The first group to LDS, the next loads out, then group by group.
-    put(std::integral_constant<int, 0>{});
-    if constexpr (AH < UG) issue(std::integral_constant<int, AH>{});
+    // Group 0 has landed (the predictors too: the wait takes every load),
+    // and every wave is done with the guide in slot 1.
+#pragma unroll
+    for (int r = 0; r < RPT; r++)
+#pragma unroll
+        for (int m = 1; m < D; m++) asm volatile("" : : "v"(p[r][m]));
+    wait_vm0();
     __syncthreads();
     float y[RPT][3];
     static_for<UG>([&](auto uu) {
         constexpr int U = decltype(uu)::value;
+        if constexpr (U + 1 < UG) issue(std::integral_constant<int, U + 1>{});
         const float4 *const slot = s_ring + (U % 2) * kBlendRN;
         float acc[RPT][4];
 #pragma unroll
@@ -1068,9 +1091,9 @@ blend_kernel(const BlendArgs a)
             }
         }
         if constexpr (U + 1 < UG) {
+            // group U + 1 has landed, and every wave is done with slot U % 2
             __builtin_amdgcn_sched_barrier(0);
-            put(std::integral_constant<int, U + 1>{});
-            if constexpr (U + 1 + AH < UG) issue(std::integral_constant<int, U + 1 + AH>{});
+            wait_vm0();
             __syncthreads();
         }
     });
