@@ -1097,16 +1097,24 @@ blend_kernel(const BlendArgs a)
             __syncthreads();
         }
     });
-    // Stores without a branch (a pixel outside the image gets an offset past
-    // the array, which the buffer drops): behind a branch, the compiler sinks
-    // the whole accumulation into it and holds every LDS read at once.
+    // Stores for the pixels inside the image only.  Every value is complete
+    // before the branch (an empty asm takes each one): behind a plain branch,
+    // the compiler sank the whole accumulation into it and held every LDS
+    // read at once.
     const Rsrc r_out = array_rsrc(a.out, 3u * n * 4u);
+    float v[RPT][3];
 #pragma unroll
-    for (int r = 0; r < RPT; r++) {
-        const uint32_t vo = mine[r] ? jr[r] * 4u : 0x80000000u;
+    for (int r = 0; r < RPT; r++)
 #pragma unroll
-        for (int c = 0; c < 3; c++) bstore(r_out, vo, (uint32_t)c * n * 4u, y[r][c] * inv_den[r]);
-    }
+        for (int c = 0; c < 3; c++) {
+            v[r][c] = y[r][c] * inv_den[r];
+            asm volatile("" : "+v"(v[r][c]));
+        }
+#pragma unroll
+    for (int r = 0; r < RPT; r++)
+        if (mine[r])
+#pragma unroll
+            for (int c = 0; c < 3; c++) bstore(r_out, jr[r] * 4u, (uint32_t)c * n * 4u, v[r][c]);
 }
 
 // A part of a batched step's frame table, passed by value as a kernel

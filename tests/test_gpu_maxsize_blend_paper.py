@@ -140,3 +140,56 @@ def test_paper_step_and_blend_at_maximum_size():
         assert e <= G1_TOL and eb <= G1_TOL, ((x0, y0), e, eb)
     s.close()
     torch.cuda.synchronize()
+
+
+def test_blend_d1_output_beyond_2gib_ragged_tiles():
+    """d = 1 allows images whose output is larger than 2 GiB (3 x 14000 x
+    12800 floats, 2.15 GB) with a ragged last tile column (14000 = 218.75
+    tiles of 64): no store of the tile's lanes outside the image may land in
+    the output.  Windows against the oracle, among them the one around the
+    blue-plane pixel at byte offset 2^31 of the output, where a store meant
+    to fall past the array would land if its offset only cleared 2 GiB."""
+    import oracle
+    import torch
+    from paper_2106_08034_amd import wrls
+    W, H, d = 14000, 12800, 1
+    n = W * H
+    assert 12 * n > 1 << 31
+    p = wrls.make_params(W, H, d)
+    assert wrls.wrls_params_validate(p) == 0
+    log("case blend d=1 %dx%d, output %.2f GB" % (W, H, 12 * n / 1e9))
+    g = torch.Generator(device="cuda").manual_seed(13)
+    s = wrls.Stream(W, H, d)
+    out = torch.empty((3, H, W), device="cuda")
+    for _ in range(2):
+        color = torch.rand((3, H, W), device="cuda", generator=g) * 1.5
+        var = torch.rand((H, W), device="cuda", generator=g) * 0.2 + 0.01
+        mot = torch.empty((2, H, W), device="cuda")
+        mot[0].fill_(-0.7)
+        mot[1].fill_(0.4)
+        s.step(color, None, var, mot, out=out)
+        del color, var, mot
+    fin = s.blend(None, out, 1.5, 0.15)
+    P, B = s.get_state()
+    torch.cuda.synchronize()
+    k = ((1 << 31) - 8 * n) // 4            # blue-plane pixel at output byte 2^31
+    yk, xk = divmod(k, W)
+    wins = [(max(0, min(W - WIN_W, xk - WIN_W // 2)), max(0, min(H - WIN_H, yk - WIN_H // 2))),
+            (W - WIN_W, H - WIN_H), (W - WIN_W, 0), (W // 2, H // 2)]
+    for (x0, y0) in wins:
+        cx0, cy0 = max(0, x0 - MARGIN), max(0, y0 - MARGIN)
+        cx1, cy1 = min(W, x0 + WIN_W + MARGIN), min(H, y0 + WIN_H + MARGIN)
+        c = (cx0, cy0, cx1, cy1)
+        o = oracle.Oracle(cx1 - cx0, cy1 - cy0, d)
+        Bc = _crop(B, c)
+        o.set_state(unpack_P(_crop(P, c), d), Bc, frames=2)
+        ref = o.blend(None, 1.5, 0.15)
+        wy, wx = slice(y0 - cy0, y0 - cy0 + WIN_H), slice(x0 - cx0, x0 - cx0 + WIN_W)
+        got = fin[:, y0:y0 + WIN_H, x0:x0 + WIN_W].cpu().numpy()
+        pr = np.ones((1,) + ref.shape[1:])
+        e = g1(got, ref[:, wy, wx], blend_scale(Bc.astype(np.float64), pr)[:, wy, wx])
+        log("  window (%d, %d): blend error %.3g" % (x0, y0, e))
+        assert e <= G1_TOL, ((x0, y0), e)
+    s.close()
+    del out, fin, P, B
+    torch.cuda.synchronize()
