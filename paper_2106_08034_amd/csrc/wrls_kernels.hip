@@ -764,6 +764,7 @@ batch_kernel(const BatchTable *__restrict__ tab)
     for (int k = 1; k <= kMaxBatch; k++) f += (k <= n && tab->prefix[k] <= t0 + r) ? 1 : 0;
     for (int t = t0 + r; t < t1; t += on_xcd) {
         while (expect(f < n, kChkBatchFrame) && t >= tab->prefix[f + 1]) f++;
+        if (!expect(f < n, kChkBatchFrame)) break;  // a table that covers no such tile
         const FrameArgs a = tab->frame[f];
         const int local = t - tab->prefix[f];
         const int ty = local / a.tiles_x;
@@ -836,7 +837,7 @@ __device__ __forceinline__ void static_for(F &&f)
 // lds + 16 l + 15, M0 holding the wave's LDS base; lanes outside the exec
 // mask write nothing.  Inline assembly, because the compiler makes every
 // LDS read after such a load wait for all of them to land, a wait the blend
-// places itself (wait_vm).  The asm has no register output, and M0 is used
+// places itself (wait_vm0).  The asm has no register output, and M0 is used
 // by nothing else in the kernels (the compiler notes that it does not
 // preserve a reserved register named as clobbered; nothing here needs it
 // to).
