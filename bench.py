@@ -381,7 +381,8 @@ def bench_serving(args, modes=("batched", "per_stream"), saturating=True):
             srv = Server(budget_bytes=budget, max_batch=32, per_stream=mode == "per_stream",
                          tile=tuple(args.serve_tile))
             rec_sid = small.sid if (name == "c5" and mode == "batched") else None
-            res, rec = srv.run(sessions, pools, seconds=seconds, record=rec_sid, record_frames=20)
+            res, rec = srv.run(sessions, pools, seconds=seconds, record=rec_sid, record_frames=20,
+                               poll=args.serve_poll_us * 1e-6)
             if rec_sid is not None:
                 recorded = rec
             res["budget_gb"] = round(budget / (1 << 30), 2)
@@ -398,7 +399,7 @@ def bench_serving(args, modes=("batched", "per_stream"), saturating=True):
             for mode in modes:
                 srv = Server(budget_bytes=budget, max_batch=32, tile=tuple(args.serve_tile),
                              rate_budget=rate_budget, per_stream=mode == "per_stream")
-                res, _ = srv.run(sessions, pools, seconds=seconds)
+                res, _ = srv.run(sessions, pools, seconds=seconds, poll=args.serve_poll_us * 1e-6)
                 res["budget_gb"] = round(budget / (1 << 30), 2)
                 out[name + "_rate_admission"] = out.get(name + "_rate_admission", {})
                 out[name + "_rate_admission"][mode] = res
@@ -832,6 +833,9 @@ def main():
                          "without the blend (ablation_c3: on the c3 scene with its edits)")
     ap.add_argument("--headline-only", action="store_true",
                     help="c3: skip the c2, c4 and serving legs")
+    ap.add_argument("--serve-poll-us", type=float, default=0.0,
+                    help="serving: host sleep between polls when nothing was launched (0: busy poll, "
+                         "the default: a sleep costs the loop's latency its granularity)")
     ap.add_argument("--serve-seconds", type=float, default=12.0,
                     help="wall seconds of serving the 32-session trace, per mode")
     ap.add_argument("--saturating-seconds", type=float, default=8.0,

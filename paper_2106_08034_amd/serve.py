@@ -299,12 +299,14 @@ class Server:
         self.created.pop(s.sid, None)
 
     def run(self, sessions, frame_pools, seconds: float, record: Optional[int] = None,
-            poll: float = 2e-4, record_frames: Optional[int] = None):
+            poll: float = 0.0, record_frames: Optional[int] = None):
         """sessions: synth.Session list; frame_pools[(w, h)]: list of device
         frame tuples, cycled.  Runs until `seconds` have passed or every
         session is served.  record: sid whose outputs are kept (host copies)
         for the alone-vs-mix and oracle checks, its first record_frames
-        frames (None: all)."""
+        frames (None: all).  poll: seconds to sleep when a pass launched
+        nothing; 0 (the default) polls without sleeping, since a sleep adds
+        its granularity (0.1-0.3 ms here) to every frame's latency."""
         torch = self.torch
         pending = sorted([SessionState(x.sid, x.width, x.height, x.fps, x.arrival,
                                        x.arrival + x.duration) for x in sessions],
