@@ -5,8 +5,9 @@ failing access is skipped and its site flagged).  It runs edge cases that
 push the addressing to its limits: degenerate and ragged shapes, every d,
 both input types, bilinear and nearest reprojection, motion that lands
 exactly on the image border, just outside it, far outside it, or is not
-finite; the spatial blend (strip tile order at 4K), paper mode, the traffic
-probe, batched steps on both grids and the allocation-free batched step.
+finite; the full-size scenes (the spatial blend in strip order at 4K), paper
+mode, the traffic probe, batched steps on both grids and the allocation-free
+batched step.
 Bar: no site flagged, and every output and final state bitwise equal to the
 shipped library's on the same inputs."""
 import os
@@ -157,15 +158,20 @@ def test_checked_paper_mode_and_tiles(libs):
                                           tile))
 
 
-def test_checked_4k_blend_in_strips(libs):
-    wl = synth.c3(frames=2)
+@pytest.mark.parametrize("scene", ["c3", "c2", "c2_paper"])
+def test_checked_full_size_scenes(libs, scene):
+    # 4K d = 10 FP16 (the blend in strips), 1080p d = 8 FP32 and 1080p paper
+    # mode, with the scenes' own motion fields and disocclusions
+    wl = synth.c3(frames=3) if scene == "c3" else synth.c2(frames=3)
     src = synth.FrameSource(wl)
     frames = []
-    for _ in range(2):
+    for _ in range(3):
         f = src.next()
         frames.append((f.color, f.feats, f.var, f.motion))
-    _compare(libs, "4K d=10 f16",
-             lambda wrls, L: _run(wrls, L, wl.width, wl.height, wl.d, True, frames, "invvar",
+    paper = scene == "c2_paper"
+    _compare(libs, "%s %dx%d" % (scene, wl.width, wl.height),
+             lambda wrls, L: _run(wrls, L, wl.width, wl.height, 4 if paper else wl.d,
+                                  wl.in_dtype == "f16", frames, "paper" if paper else "invvar",
                                   "bilinear"))
 
 
