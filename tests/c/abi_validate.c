@@ -96,6 +96,11 @@ int main(void)
     EXPECT(wrls_device_copy(buf, buf + 32, 0, NULL) == WRLS_OK);
     EXPECT(wrls_device_copy(NULL, buf, 16, NULL) == WRLS_EINVAL);
     EXPECT(wrls_device_copy(buf + 1, buf + 33, 16, NULL) == WRLS_EINVAL);   /* misaligned */
+    EXPECT(wrls_traffic_probe(NULL, NULL, NULL, NULL, NULL, NULL) == WRLS_EINVAL);
+    EXPECT(wrls_checked_build() == 0);
+    uint32_t flags = 7u;
+    EXPECT(wrls_checked_failures(&flags) == WRLS_EUNSUPPORTED && flags == 7u);
+    EXPECT(wrls_checked_raise(1u, NULL) == WRLS_EUNSUPPORTED);
     EXPECT(strncmp(wrls_version(), "libwrls", 7) == 0);
     printf("abi validate: %s\n", bad ? "FAILED" : "ok");
     return bad != 0;
